@@ -1,0 +1,276 @@
+/*
+ * lope.h — C ABI of the LOPe stencil-sweep library for AMD Instinct MI355X (gfx950).
+ *
+ * The library applies a locally-oriented update to every interior element of
+ * a 1-3D grid: each element is rewritten only from a read-only neighbourhood
+ * (its halo) of the state at invocation time, the halo is given by a boundary
+ * rule, and sweeps are iterated Jacobi-style with two buffers.  The paper
+ * (Rasmussen, Sottile, Nagle, Rasmussen, "Locally-Oriented Programming")
+ * defines the pieces this interface is built from:
+ *   - halo regions and their width (section 2.2, "Halo regions");
+ *   - the local element and its read-only neighbours, zero-based offsets with
+ *     the first index running left/right and the second below/above
+ *     (section 2.2, "LOPe index notation"; Fig. 1);
+ *   - the concurrent sweep over the interior with race freedom by double
+ *     buffering (section 2.2, "Concurrent functions"; section 3.2, items 1-7);
+ *   - the halo transfer with a boundary rule kept apart from the algorithm
+ *     (section 3.2, HALO_TRANSFER(U, BC=CYCLIC); section 3.4, first item);
+ *   - the constraints checked at run time here: no store to the halo, no out
+ *     of bounds access, no race (section 3.5);
+ *   - a device query that falls back to the host (section 3.1, GET_SUBIMAGE).
+ *
+ * Conventions for every call:
+ *   - Non-owning: the caller owns all grid memory (device memory, e.g. from
+ *     PyTorch's allocator) and all coefficient tables (host memory).
+ *   - Asynchronous: every compute call enqueues work on `stream` (a
+ *     hipStream_t; NULL means the legacy default stream) and returns without
+ *     synchronising; a kernel fault surfaces at the caller's next sync.
+ *   - Errors: every call returns LOPE_OK (0) or a negative lope_status.  All
+ *     structural validation runs before any HIP call; on error nothing has
+ *     been enqueued.  No exception crosses the ABI, nothing calls exit(), and
+ *     there is no CPU fallback.  lope_last_error() gives a thread-local text.
+ *   - Memory layout of a grid: padded storage with h halo cells on each side
+ *     of every used axis; x (paper axis 0, the first index) is contiguous.
+ *     Element (x, y, z), with -h <= x < n[0]+h etc., lives at
+ *     origin + x + y*stride[1] + z*stride[2] (in elements).
+ */
+#ifndef LOPE_H
+#define LOPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+typedef enum lope_status {
+    LOPE_OK = 0,
+    LOPE_ERR_INVALID_ARG = -1,    /* null pointer, bad ndim/extent/stride/dtype, mismatched grids,
+                                     pointer not device memory, or storage outside its allocation */
+    LOPE_ERR_HALO_TOO_SMALL = -2, /* stencil radius larger than the halo width h (section 3.5) */
+    LOPE_ERR_ALIAS = -3,          /* source and destination interiors overlap (section 2.2, 3.5) */
+    LOPE_ERR_UNSUPPORTED = -4,    /* valid request this build does not implement (see each call) */
+    LOPE_ERR_NO_DEVICE = -5,      /* no usable GPU (or LOPE_FORCE_NO_DEVICE=1 in the environment) */
+    LOPE_ERR_HIP = -6             /* a HIP runtime error; its text is in lope_last_error() */
+} lope_status;
+
+/* Device id returned by lope_get_device when no device can be used. */
+#define LOPE_HOST (-1)
+
+/* ---- element types and boundary kinds ---------------------------------- */
+typedef enum lope_dtype { LOPE_F32 = 0, LOPE_F64 = 1 } lope_dtype;
+
+typedef enum lope_bc_kind {
+    LOPE_BC_DIRICHLET = 0,        /* every halo cell along this axis holds the grid's value g */
+    LOPE_BC_PERIODIC = 1          /* halo cells repeat the interior cyclically (BC=CYCLIC) */
+} lope_bc_kind;
+
+#define LOPE_MAX_NDIM 3
+#define LOPE_MAX_RADIUS 4
+#define LOPE_MAX_TAPS 256         /* non-zero coefficients per stencil */
+
+/* A padded grid (section 2.2 halo region; section 3.2 padded allocation).
+ *   ndim    1..3.
+ *   h       halo width in cells, the same on both sides of every used axis, >= 0.
+ *   dtype   lope_dtype.
+ *   n[a]    interior extent of axis a (a = 0 is x); >= 0; axes >= ndim must be 1.
+ *           An interior with a zero extent is empty and every call on it is a no-op.
+ *   stride  element strides; stride[0] must be 1, stride[1] >= n[0]+2h,
+ *           stride[2] >= stride[1]*(n[1]+2h) (rows and planes do not overlap).
+ *   origin  device pointer to interior element (0,0,0).  The whole padded box
+ *           must lie inside one device allocation (checked). */
+typedef struct lope_grid {
+    int32_t ndim;
+    int32_t h;
+    int32_t dtype;
+    int32_t reserved;
+    int64_t n[3];
+    int64_t stride[3];
+    void* origin;
+} lope_grid;
+
+/* Boundary rule (section 3.2, BC argument of the halo transfer).  kind[a] for
+ * each used axis; one Dirichlet value per grid.  For a halo cell that lies
+ * outside the interior along at least one Dirichlet axis the value is `value`;
+ * otherwise it is the interior value at the index wrapped on every periodic
+ * axis.  (The paper shows faces only; this order-independent rule also fixes
+ * edges and corners and mixed per-axis kinds.) */
+typedef struct lope_bc {
+    int32_t kind[3];
+    int32_t reserved;
+    double value;
+} lope_bc;
+
+/* Coefficient stencil of the local-element update (Fig. 1 generalised):
+ * y[x] = sum over offsets o in [-r, r]^ndim of c_o * B(src)[x + o].
+ * coeffs is HOST memory holding (2r+1)^ndim doubles; the entry for offset o
+ * sits at index sum_a (o_a + r) * (2r+1)^a (x fastest).  The table is copied
+ * at call time and each coefficient is rounded once to the grid dtype.  Each
+ * point's sum is evaluated as a chain of fused multiply-adds over the
+ * non-zero taps in that same index order, so every kernel variant (tiling,
+ * temporal blocking, batching) gives identical values. */
+typedef struct lope_stencil {
+    int32_t ndim;
+    int32_t radius;               /* 0..LOPE_MAX_RADIUS */
+    const double* coeffs;
+} lope_stencil;
+
+/* Spatially varying diffusion coefficient for the update
+ *   u' = u + dt * sum_a sum_{s=+-1} K^s_a (u_{x+s e_a} - u_x),
+ *   K^s_a = (kappa_x + kappa_{x + s e_a}) / 2,
+ * a local-element function with two read-only inputs (u and kappa). */
+typedef struct lope_varcoef {
+    const lope_grid* kappa;       /* same ndim, extents and dtype as u; read-only */
+    double dt;
+} lope_varcoef;
+
+/* Explicit launch choice, used by the autotuner (all zero = automatic). */
+#define LOPE_VARIANT_GENERIC (-1)
+typedef struct lope_tuning {
+    int32_t variant;              /* kernel variant id from lope_variant_info, 0 = automatic,
+                                     LOPE_VARIANT_GENERIC = the one-thread-per-point kernel */
+    int32_t tdepth;               /* sweeps fused per pass, 1..4; 0 = automatic */
+    int32_t chunk;                /* extent of the marched axis per workgroup; 0 = automatic */
+    int32_t reserved;
+} lope_tuning;
+
+/* ---- device ------------------------------------------------------------ */
+
+/* Section 3.1 (GET_SUBIMAGE): *out = ordinal if that GPU can be used, else
+ * LOPE_HOST.  Falling back to the host is not an error (returns LOPE_OK) so a
+ * program can proceed without a device; compute calls then return
+ * LOPE_ERR_NO_DEVICE.  out must not be NULL. */
+int lope_get_device(int ordinal, int* out);
+
+/* ---- halo ---------------------------------------------------------------- */
+
+/* Fill the stored halo of g from its own interior with the boundary rule
+ * (section 3.2, the halo transfer on one device).  Only halo cells are
+ * written; the interior is read.  The sweeps below do NOT need this: they
+ * apply the rule while loading, so the stored halo is never read by them. */
+int lope_halo_fill(const lope_grid* g, const lope_bc* bc, void* stream);
+
+/* ---- sweeps -------------------------------------------------------------- */
+
+/* One sweep (section 3.2, do concurrent over the interior calling the local
+ * element function): dst interior = S(B(src)).  src is never written; the
+ * halo of dst is never written.  Requires radius <= src->h, equal ndim,
+ * extents and dtype, and non-overlapping interiors. */
+int lope_apply(const lope_grid* src, const lope_grid* dst, const lope_stencil* st,
+               const lope_bc* bc, void* stream);
+
+/* n_steps sweeps alternating between a and b (section 3.2, the loop around
+ * the sweep and the halo transfer; double buffering per section 2.2).  The
+ * initial state is a's interior.  Several sweeps may be fused per pass over
+ * memory (tdepth, 0 = automatic); the result is identical.  *result_index is
+ * set to 0 if the final state is in a, 1 if in b (n_steps mod 2 when one
+ * sweep runs per pass).  Both grids need h >= radius.  result_index must not
+ * be NULL. */
+int lope_iterate(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
+                 const lope_bc* bc, int64_t n_steps, int32_t tdepth, void* stream,
+                 int32_t* result_index);
+
+/* lope_iterate with an explicit kernel variant / depth / chunk (autotuner). */
+int lope_iterate_tuned(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
+                       const lope_bc* bc, int64_t n_steps, const lope_tuning* tune,
+                       void* stream, int32_t* result_index);
+
+/* Adjoint sweep: xbar interior = S^T(ybar), the transpose of the linear part
+ * of lope_apply: the reflected stencil c_{-o} applied with the transposed
+ * rule (periodic axes wrap; Dirichlet halo cells contribute zero).  If
+ * gbar_dirichlet is not NULL it is a DEVICE pointer to one double that
+ * receives (overwritten) dL/dg = sum_x ybar[x] * (sum of c_o over the taps of
+ * x that read a Dirichlet halo cell). */
+int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_stencil* st,
+                       const lope_bc* bc, double* gbar_dirichlet, void* stream);
+
+/* ---- variable-coefficient diffusion (3D, periodic) ------------------------ */
+
+/* dst = src + dt * div(kappa grad src) with arithmetic-mean faces (see
+ * lope_varcoef).  3D only, every axis periodic (else LOPE_ERR_UNSUPPORTED);
+ * h >= 1 on src and kappa. */
+int lope_apply_var(const lope_grid* src, const lope_grid* dst, const lope_varcoef* vc,
+                   const lope_bc* bc, void* stream);
+
+/* Reverse step of lope_apply_var at state u_t, given lam_next = dL/du_{t+1}:
+ *   lam[x]    = lam_next[x] + dt * sum_{a,s} K^s_a(x) (lam_next[x+s e_a] - lam_next[x])
+ *               (the step matrix is symmetric, so this is its transpose);
+ *   gkappa[x] += dt/2 * sum_{a,s} (u_t[x+s e_a] - u_t[x]) (lam_next[x] - lam_next[x+s e_a]).
+ * gkappa is a grid of the same extents, dtype F32 or F64 (accumulated in its
+ * own precision; fold F32 partial sums into F64 with lope_accumulate).  lam
+ * must not overlap lam_next, u_t, kappa or gkappa. */
+int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, const lope_grid* u_t,
+                           const lope_varcoef* vc, const lope_bc* bc, const lope_grid* gkappa,
+                           void* stream);
+
+/* total (F64) += partial (F32 or F64) over the interior, then partial = 0. */
+int lope_accumulate(const lope_grid* partial, const lope_grid* total, void* stream);
+
+/* ---- batches: many independent grids in one persistent launch ------------- */
+
+/* One grid of a batch: a 2D sweep from src to dst (both padded grids),
+ * iterated with its own stencil and rule.  The state alternates between src
+ * and dst exactly as in lope_iterate with one sweep per pass. */
+typedef struct lope_batch_item {
+    lope_grid src;
+    lope_grid dst;
+    lope_stencil stencil;         /* 2D, radius 1; copied at plan creation */
+    lope_bc bc;
+} lope_batch_item;
+
+typedef struct lope_batch_plan lope_batch_plan;
+
+/* Build a plan for n_items grids and n_steps sweeps each: validates every
+ * item, builds the tile work list, uploads it (the plan owns this device
+ * memory), and captures the persistent launch into a HIP graph on `stream`.
+ * The plan borrows the grids' memory until it is destroyed.  Supports 2D
+ * grids with radius-1 stencils of at most 9 taps (else LOPE_ERR_UNSUPPORTED). */
+int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_t n_steps,
+                           void* stream, lope_batch_plan** out);
+
+/* Launch the plan's graph on `stream`: every grid advances n_steps sweeps;
+ * grid i ends in its src if n_steps is even, else in its dst. */
+int lope_batch_apply(lope_batch_plan* plan, void* stream);
+
+/* Same work as lope_batch_apply as ordinary kernel launches, one per grid
+ * per sweep (the baseline the persistent launch is compared with). */
+int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream);
+
+/* Synchronise `stream` and report whether the last launch of the plan hit
+ * its internal wait bound (a broken scheduling invariant): *out = 0 when all
+ * work completed, 1 otherwise.  out must not be NULL. */
+int lope_batch_plan_error(lope_batch_plan* plan, void* stream, int* out);
+
+/* Release the plan's device memory and graph (waits for nothing: the caller
+ * synchronises first if the plan may still be running). NULL is a no-op. */
+int lope_batch_plan_destroy(lope_batch_plan* plan);
+
+/* ---- introspection --------------------------------------------------------- */
+
+/* Text of a status code (static storage). */
+const char* lope_status_string(int status);
+
+/* Thread-local text of the last error raised on this thread ("" if none). */
+const char* lope_last_error(void);
+
+/* Number of compiled kernel variants, and the description of variant id
+ * (1..count): fills `text` (NUL-terminated, at most cap bytes) with
+ * "name ndim=.. radius=.. tdepth=.. dtype=.. shape=.. tile=..". */
+int lope_variant_count(void);
+int lope_variant_info(int id, char* text, int cap);
+
+/* Id of the kernel variant lope_iterate would use for one pass with tdepth
+ * sweeps (0 = automatic) on this grid/stencil, or a negative status. */
+int lope_select_variant(const lope_grid* g, const lope_stencil* st, int32_t tdepth);
+
+/* Register an automatic choice: for grids and stencils like (g, st), use
+ * tune->variant, tune->tdepth and tune->chunk.  The key is (ndim, radius,
+ * dtype, star/box shape, size bucket = floor(log2(interior points))). */
+int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning* tune);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOPE_H */

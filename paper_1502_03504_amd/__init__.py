@@ -1,0 +1,307 @@
+"""MI355X-native LOPe stencil sweeps: Python binding of liblope.so.
+
+The functions below keep the names of the C ABI (include/lope.h) and only
+marshal arguments: every step of the computation runs in the library's HIP
+kernels.  PyTorch provides device memory and the current stream.  Importing
+this package fails loudly if the library has not been built.
+
+Arrays use numpy/torch axis order: a 3D interior has shape (nz, ny, nx), so
+the paper's first index x (left/right, contiguous in memory) is the last
+tensor axis.  Boundary kinds are given per paper axis, x first.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import LopeError, check, load
+
+__all__ = [
+    "Grid", "LopeError", "lope_get_device", "lope_halo_fill", "lope_apply", "lope_iterate",
+    "lope_iterate_tuned", "lope_apply_adjoint", "lope_apply_var", "lope_apply_var_adjoint",
+    "lope_accumulate", "lope_variant_count", "lope_variant_info", "lope_select_variant",
+    "lope_tune_set", "variants", "BatchPlan", "lope_batch_plan_create", "lope_batch_apply",
+    "lope_batch_apply_per_grid", "lope_batch_plan_destroy", "DIRICHLET", "PERIODIC",
+]
+
+DIRICHLET = "dirichlet"
+PERIODIC = "periodic"
+
+_ALIGN_BYTES = 128
+
+
+def library_path() -> str:
+    """Load the HIP library (raises ImportError if it is not built) and return its path."""
+    load()
+    return _lib.LIB_PATH
+
+
+def _dtype_code(dtype) -> int:
+    if dtype == torch.float32:
+        return _lib.LOPE_F32
+    if dtype == torch.float64:
+        return _lib.LOPE_F64
+    raise TypeError("grids hold float32 or float64, not %s" % dtype)
+
+
+def _align(v: int, a: int) -> int:
+    return (v + a - 1) // a * a
+
+
+class Grid:
+    """A padded grid in device memory: interior plus h halo cells per side.
+
+    Storage layout (the padded allocation of section 3.2, x contiguous): each
+    row starts ``lead`` elements before interior x = 0 (lead >= h, rounded so
+    the interior row start is 128-byte aligned), rows are ``sy`` elements apart
+    (a multiple of 128 bytes) and planes ``sz`` apart.
+    """
+
+    def __init__(self, storage: torch.Tensor, shape, h: int, lead: int, sy: int, sz: int):
+        self.storage = storage
+        self.shape = tuple(int(s) for s in shape)
+        self.ndim = len(self.shape)
+        self.h = int(h)
+        self.lead = int(lead)
+        self.sy = int(sy)
+        self.sz = int(sz)
+        d = self.ndim
+        self.offset = self.lead + (self.h * self.sy if d >= 2 else 0) + (self.h * self.sz if d >= 3 else 0)
+        if storage.dim() != 1:
+            raise ValueError("storage must be a flat tensor")
+        nx = self.shape[-1]
+        if self.lead < self.h or (d >= 2 and self.sy < self.lead + nx + self.h) or \
+                (d >= 3 and self.sz < self.sy * (self.shape[-2] + 2 * self.h)):
+            raise ValueError("strides do not hold the padded rows/planes")
+        last = self.offset + nx - 1 + self.h
+        if d >= 2:
+            last += (self.shape[-2] - 1 + self.h) * self.sy
+        if d >= 3:
+            last += (self.shape[-3] - 1 + self.h) * self.sz
+        first = self.offset - self.h - (self.h * self.sy if d >= 2 else 0) - (self.h * self.sz if d >= 3 else 0)
+        if min(self.shape) > 0 and (first < 0 or last >= storage.numel()):
+            raise ValueError("storage of %d elements does not hold the padded box" % storage.numel())
+
+    # ---- construction ----
+    @classmethod
+    def allocate(cls, shape, h: int, dtype=torch.float32, device="cuda", halo_src=None, fill=0.0):
+        """New padded grid; with ``halo_src`` (a tensor or Grid) its interior is
+        copied in, like allocating with HALO_SRC in section 3.2."""
+        shape = tuple(int(s) for s in shape)
+        if not 1 <= len(shape) <= 3:
+            raise ValueError("1..3 dimensions")
+        esize = torch.empty((), dtype=dtype).element_size()
+        a = _ALIGN_BYTES // esize
+        nx = shape[-1]
+        lead = _align(h, a) if h > 0 else 0
+        sy = _align(lead + nx + h, a)
+        d = len(shape)
+        ny = shape[-2] if d >= 2 else 1
+        nz = shape[-3] if d >= 3 else 1
+        rows = (ny + 2 * h) if d >= 2 else 1
+        sz = sy * rows
+        planes = (nz + 2 * h) if d >= 3 else 1
+        storage = torch.full((sz * planes,), float(fill), dtype=dtype, device=device)
+        g = cls(storage, shape, h, lead, sy, sz)
+        if halo_src is not None:
+            src = halo_src.interior() if isinstance(halo_src, Grid) else halo_src
+            g.interior().copy_(torch.as_tensor(src).to(device=device, dtype=dtype))
+        return g
+
+    @classmethod
+    def from_array(cls, arr, h: int, device="cuda", dtype=None):
+        arr = np.asarray(arr)
+        tdt = dtype or (torch.float64 if arr.dtype == np.float64 else torch.float32)
+        return cls.allocate(arr.shape, h, tdt, device, halo_src=torch.from_numpy(np.ascontiguousarray(arr)))
+
+    def empty_like(self, h=None):
+        return Grid.allocate(self.shape, self.h if h is None else h, self.dtype, self.storage.device)
+
+    # ---- views ----
+    @property
+    def dtype(self):
+        return self.storage.dtype
+
+    def _strides(self):
+        return {1: (1,), 2: (self.sy, 1), 3: (self.sz, self.sy, 1)}[self.ndim]
+
+    def interior(self) -> torch.Tensor:
+        return self.storage.as_strided(self.shape, self._strides(), self.offset)
+
+    def padded(self) -> torch.Tensor:
+        h = self.h
+        shp = tuple(s + 2 * h for s in self.shape)
+        d = self.ndim
+        off = self.offset - h - (h * self.sy if d >= 2 else 0) - (h * self.sz if d >= 3 else 0)
+        return self.storage.as_strided(shp, self._strides(), off)
+
+    def numpy(self) -> np.ndarray:
+        return self.interior().detach().cpu().numpy().copy()
+
+    def descriptor(self) -> _lib.lope_grid:
+        g = _lib.lope_grid()
+        g.ndim = self.ndim
+        g.h = self.h
+        g.dtype = _dtype_code(self.dtype)
+        n = list(reversed(self.shape)) + [1] * (3 - self.ndim)
+        for a in range(3):
+            g.n[a] = n[a]
+        g.stride[0] = 1
+        g.stride[1] = self.sy if self.ndim >= 2 else 0
+        g.stride[2] = self.sz if self.ndim >= 3 else 0
+        g.origin = self.storage.data_ptr() + self.offset * self.storage.element_size()
+        return g
+
+
+# ---- argument marshalling ----
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _bc(bc, ndim: int) -> _lib.lope_bc:
+    """bc: an object with .kinds/.value, a (kinds, value) pair or a kinds tuple."""
+    if hasattr(bc, "kinds"):
+        kinds, value = bc.kinds, bc.value
+    elif isinstance(bc, (tuple, list)) and len(bc) == 2 and not isinstance(bc[0], str):
+        kinds, value = bc
+    else:
+        kinds, value = bc, 0.0
+    out = _lib.lope_bc()
+    for a in range(3):
+        k = kinds[a] if a < len(kinds) else PERIODIC
+        if isinstance(k, str):
+            k = {DIRICHLET: _lib.LOPE_BC_DIRICHLET, PERIODIC: _lib.LOPE_BC_PERIODIC}[k]
+        out.kind[a] = int(k)
+    out.value = float(value)
+    return out
+
+
+class _Stencil:
+    """Keeps the host coefficient table alive for the duration of a call."""
+
+    def __init__(self, st):
+        coeffs = st.coeffs if hasattr(st, "coeffs") else st
+        self.arr = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+        r = (self.arr.shape[0] - 1) // 2 if self.arr.ndim else 0
+        self.c = _lib.lope_stencil()
+        self.c.ndim = int(getattr(st, "ndim", self.arr.ndim))
+        self.c.radius = int(getattr(st, "radius", r))
+        self.c.coeffs = self.arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ref(x):
+    return ctypes.byref(x)
+
+
+# ---- the C ABI, by name ----
+def lope_get_device(ordinal: int = 0) -> int:
+    out = ctypes.c_int(-2)
+    check(load().lope_get_device(int(ordinal), _ref(out)))
+    return out.value
+
+
+def lope_halo_fill(grid: Grid, bc, stream=None) -> None:
+    g = grid.descriptor()
+    check(load().lope_halo_fill(_ref(g), _ref(_bc(bc, grid.ndim)), _stream(stream)))
+
+
+def lope_apply(src: Grid, dst: Grid, stencil, bc, stream=None) -> None:
+    s = _Stencil(stencil)
+    a, b = src.descriptor(), dst.descriptor()
+    check(load().lope_apply(_ref(a), _ref(b), _ref(s.c), _ref(_bc(bc, src.ndim)), _stream(stream)))
+
+
+def lope_iterate(a: Grid, b: Grid, stencil, bc, n_steps: int, tdepth: int = 0, stream=None) -> int:
+    """Returns 0 if the final state is in ``a``, 1 if in ``b``."""
+    s = _Stencil(stencil)
+    ga, gb = a.descriptor(), b.descriptor()
+    idx = ctypes.c_int32(-1)
+    check(load().lope_iterate(_ref(ga), _ref(gb), _ref(s.c), _ref(_bc(bc, a.ndim)), int(n_steps), int(tdepth),
+                              _stream(stream), _ref(idx)))
+    return idx.value
+
+
+def lope_iterate_tuned(a: Grid, b: Grid, stencil, bc, n_steps: int, variant: int = 0, tdepth: int = 0,
+                       chunk: int = 0, stream=None) -> int:
+    s = _Stencil(stencil)
+    ga, gb = a.descriptor(), b.descriptor()
+    t = _lib.lope_tuning(int(variant), int(tdepth), int(chunk), 0)
+    idx = ctypes.c_int32(-1)
+    check(load().lope_iterate_tuned(_ref(ga), _ref(gb), _ref(s.c), _ref(_bc(bc, a.ndim)), int(n_steps), _ref(t),
+                                    _stream(stream), _ref(idx)))
+    return idx.value
+
+
+def lope_apply_adjoint(ybar: Grid, xbar: Grid, stencil, bc, gbar: torch.Tensor = None, stream=None) -> None:
+    """xbar = S^T ybar; if ``gbar`` (a float64 device tensor of one element) is
+    given it receives dL/dg."""
+    s = _Stencil(stencil)
+    a, b = ybar.descriptor(), xbar.descriptor()
+    gp = None
+    if gbar is not None:
+        if gbar.dtype != torch.float64 or gbar.numel() < 1 or not gbar.is_cuda:
+            raise TypeError("gbar must be a float64 device tensor")
+        gp = ctypes.c_void_p(gbar.data_ptr())
+    check(load().lope_apply_adjoint(_ref(a), _ref(b), _ref(s.c), _ref(_bc(bc, ybar.ndim)), gp, _stream(stream)))
+
+
+def _varcoef(kappa: Grid, dt: float):
+    kd = kappa.descriptor()
+    vc = _lib.lope_varcoef(ctypes.pointer(kd), float(dt))
+    return kd, vc
+
+
+def lope_apply_var(src: Grid, dst: Grid, kappa: Grid, dt: float, bc, stream=None) -> None:
+    kd, vc = _varcoef(kappa, dt)
+    a, b = src.descriptor(), dst.descriptor()
+    check(load().lope_apply_var(_ref(a), _ref(b), _ref(vc), _ref(_bc(bc, src.ndim)), _stream(stream)))
+
+
+def lope_apply_var_adjoint(lam_next: Grid, lam: Grid, u_t: Grid, kappa: Grid, dt: float, bc, gkappa: Grid,
+                           stream=None) -> None:
+    kd, vc = _varcoef(kappa, dt)
+    a, b, u, g = lam_next.descriptor(), lam.descriptor(), u_t.descriptor(), gkappa.descriptor()
+    check(load().lope_apply_var_adjoint(_ref(a), _ref(b), _ref(u), _ref(vc), _ref(_bc(bc, 3)), _ref(g),
+                                        _stream(stream)))
+
+
+def lope_accumulate(partial: Grid, total: Grid, stream=None) -> None:
+    a, b = partial.descriptor(), total.descriptor()
+    check(load().lope_accumulate(_ref(a), _ref(b), _stream(stream)))
+
+
+def lope_variant_count() -> int:
+    return load().lope_variant_count()
+
+
+def lope_variant_info(vid: int) -> str:
+    buf = ctypes.create_string_buffer(256)
+    check(load().lope_variant_info(int(vid), buf, 256))
+    return buf.value.decode()
+
+
+def variants():
+    return [lope_variant_info(i) for i in range(1, lope_variant_count() + 1)]
+
+
+def lope_select_variant(grid: Grid, stencil, tdepth: int = 0) -> int:
+    s = _Stencil(stencil)
+    g = grid.descriptor()
+    return check(load().lope_select_variant(_ref(g), _ref(s.c), int(tdepth)))
+
+
+def lope_tune_set(grid: Grid, stencil, variant: int, tdepth: int = 0, chunk: int = 0) -> None:
+    s = _Stencil(stencil)
+    g = grid.descriptor()
+    t = _lib.lope_tuning(int(variant), int(tdepth), int(chunk), 0)
+    check(load().lope_tune_set(_ref(g), _ref(s.c), _ref(t)))
+
+
+from .batch import (  # noqa: E402,F401
+    BatchPlan, lope_batch_plan_create, lope_batch_apply, lope_batch_apply_per_grid, lope_batch_plan_destroy,
+)

@@ -1,0 +1,142 @@
+"""ctypes view of the C ABI declared in include/lope.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblope.so")
+
+LOPE_OK = 0
+LOPE_ERR_INVALID_ARG = -1
+LOPE_ERR_HALO_TOO_SMALL = -2
+LOPE_ERR_ALIAS = -3
+LOPE_ERR_UNSUPPORTED = -4
+LOPE_ERR_NO_DEVICE = -5
+LOPE_ERR_HIP = -6
+LOPE_HOST = -1
+
+LOPE_F32 = 0
+LOPE_F64 = 1
+LOPE_BC_DIRICHLET = 0
+LOPE_BC_PERIODIC = 1
+
+
+class lope_grid(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("h", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("stride", ctypes.c_int64 * 3),
+        ("origin", ctypes.c_void_p),
+    ]
+
+
+class lope_bc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32 * 3),
+        ("reserved", ctypes.c_int32),
+        ("value", ctypes.c_double),
+    ]
+
+
+class lope_stencil(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("radius", ctypes.c_int32),
+        ("coeffs", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class lope_varcoef(ctypes.Structure):
+    _fields_ = [
+        ("kappa", ctypes.POINTER(lope_grid)),
+        ("dt", ctypes.c_double),
+    ]
+
+
+class lope_tuning(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int32),
+        ("tdepth", ctypes.c_int32),
+        ("chunk", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class lope_batch_item(ctypes.Structure):
+    _fields_ = [
+        ("src", lope_grid),
+        ("dst", lope_grid),
+        ("stencil", lope_stencil),
+        ("bc", lope_bc),
+    ]
+
+
+P = ctypes.POINTER
+c_void_p = ctypes.c_void_p
+
+# name -> (restype, argtypes); every function declared in include/lope.h
+SIGNATURES = {
+    "lope_get_device": (ctypes.c_int, [ctypes.c_int, P(ctypes.c_int)]),
+    "lope_halo_fill": (ctypes.c_int, [P(lope_grid), P(lope_bc), c_void_p]),
+    "lope_apply": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stencil), P(lope_bc), c_void_p]),
+    "lope_iterate": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stencil), P(lope_bc), ctypes.c_int64,
+                                    ctypes.c_int32, c_void_p, P(ctypes.c_int32)]),
+    "lope_iterate_tuned": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stencil), P(lope_bc),
+                                          ctypes.c_int64, P(lope_tuning), c_void_p, P(ctypes.c_int32)]),
+    "lope_apply_adjoint": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stencil), P(lope_bc),
+                                          c_void_p, c_void_p]),
+    "lope_apply_var": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_varcoef), P(lope_bc), c_void_p]),
+    "lope_apply_var_adjoint": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_grid), P(lope_varcoef),
+                                              P(lope_bc), P(lope_grid), c_void_p]),
+    "lope_accumulate": (ctypes.c_int, [P(lope_grid), P(lope_grid), c_void_p]),
+    "lope_batch_plan_create": (ctypes.c_int, [P(lope_batch_item), ctypes.c_int64, ctypes.c_int64, c_void_p,
+                                              P(c_void_p)]),
+    "lope_batch_apply": (ctypes.c_int, [c_void_p, c_void_p]),
+    "lope_batch_apply_per_grid": (ctypes.c_int, [c_void_p, c_void_p]),
+    "lope_batch_plan_error": (ctypes.c_int, [c_void_p, c_void_p, P(ctypes.c_int)]),
+    "lope_batch_plan_destroy": (ctypes.c_int, [c_void_p]),
+    "lope_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "lope_last_error": (ctypes.c_char_p, []),
+    "lope_variant_count": (ctypes.c_int, []),
+    "lope_variant_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, ctypes.c_int]),
+    "lope_select_variant": (ctypes.c_int, [P(lope_grid), P(lope_stencil), ctypes.c_int32]),
+    "lope_tune_set": (ctypes.c_int, [P(lope_grid), P(lope_stencil), P(lope_tuning)]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load liblope.so (built in-tree); raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblope.so is not built: run `python -m paper_1502_03504_amd.build` "
+                              "(the HIP library is required; there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class LopeError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        self.code = code
+        super().__init__("%s (%d): %s" % (status_string(code), code, message))
+
+
+def status_string(code: int) -> str:
+    return load().lope_status_string(code).decode()
+
+
+def check(code: int) -> int:
+    if code < 0:
+        raise LopeError(code, load().lope_last_error().decode())
+    return code

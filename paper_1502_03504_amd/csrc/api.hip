@@ -1,0 +1,851 @@
+// C ABI: argument validation (the run-time form of the paper's section 3.5
+// constraints), kernel selection, ping-pong iteration, tuning table.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lope_internal.h"
+
+using namespace lope;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(LOPE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t elem_size(int dtype) { return dtype == LOPE_F64 ? 8 : 4; }
+
+// ---- structural checks (no HIP calls) ----
+int check_grid(const lope_grid* g, const char* name) {
+    if (!g) return fail(LOPE_ERR_INVALID_ARG, "%s: null grid", name);
+    if (g->ndim < 1 || g->ndim > 3) return fail(LOPE_ERR_INVALID_ARG, "%s: ndim %d not in 1..3", name, g->ndim);
+    if (g->dtype != LOPE_F32 && g->dtype != LOPE_F64)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: unknown dtype %d", name, g->dtype);
+    if (g->h < 0 || g->h > (1 << 20)) return fail(LOPE_ERR_INVALID_ARG, "%s: bad halo width %d", name, g->h);
+    for (int a = 0; a < 3; ++a) {
+        if (a < g->ndim) {
+            if (g->n[a] < 0 || g->n[a] > (int64_t)1 << 30)
+                return fail(LOPE_ERR_INVALID_ARG, "%s: extent n[%d]=%lld out of range", name, a, (long long)g->n[a]);
+        } else if (g->n[a] != 1) {
+            return fail(LOPE_ERR_INVALID_ARG, "%s: unused axis %d must have extent 1", name, a);
+        }
+    }
+    if (g->stride[0] != 1) return fail(LOPE_ERR_INVALID_ARG, "%s: stride[0] must be 1", name);
+    const int64_t h = g->h;
+    if (g->ndim >= 2 && g->stride[1] < g->n[0] + 2 * h)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: stride[1]=%lld < n[0]+2h", name, (long long)g->stride[1]);
+    if (g->ndim >= 3 && g->stride[2] < g->stride[1] * (g->n[1] + 2 * h))
+        return fail(LOPE_ERR_INVALID_ARG, "%s: stride[2]=%lld < stride[1]*(n[1]+2h)", name, (long long)g->stride[2]);
+    if (!g->origin) return fail(LOPE_ERR_INVALID_ARG, "%s: null origin", name);
+    return LOPE_OK;
+}
+
+bool is_empty(const lope_grid* g) { return g->n[0] == 0 || g->n[1] == 0 || g->n[2] == 0; }
+
+int check_bc(const lope_bc* bc, int ndim) {
+    if (!bc) return fail(LOPE_ERR_INVALID_ARG, "null boundary rule");
+    for (int a = 0; a < ndim; ++a)
+        if (bc->kind[a] != LOPE_BC_DIRICHLET && bc->kind[a] != LOPE_BC_PERIODIC)
+            return fail(LOPE_ERR_INVALID_ARG, "boundary kind[%d]=%d unknown", a, bc->kind[a]);
+    return LOPE_OK;
+}
+
+int check_same(const lope_grid* a, const lope_grid* b, const char* an, const char* bn) {
+    if (a->ndim != b->ndim || a->dtype != b->dtype)
+        return fail(LOPE_ERR_INVALID_ARG, "%s and %s differ in ndim or dtype", an, bn);
+    for (int k = 0; k < 3; ++k)
+        if (a->n[k] != b->n[k]) return fail(LOPE_ERR_INVALID_ARG, "%s and %s differ in extents", an, bn);
+    return LOPE_OK;
+}
+
+// Byte span [lo, hi) of a grid's interior or whole padded box.
+void span(const lope_grid* g, bool padded, uintptr_t* lo, uintptr_t* hi) {
+    const int64_t es = (int64_t)elem_size(g->dtype);
+    int64_t first = 0, last = 0;
+    for (int a = 0; a < g->ndim; ++a) {
+        const int64_t w = padded ? g->h : 0;
+        first -= w * g->stride[a];
+        last += (g->n[a] - 1 + w) * g->stride[a];
+    }
+    *lo = (uintptr_t)((const char*)g->origin + first * es);
+    *hi = (uintptr_t)((const char*)g->origin + (last + 1) * es);
+}
+
+int check_alias(const lope_grid* a, const lope_grid* b, const char* an, const char* bn) {
+    uintptr_t alo, ahi, blo, bhi;
+    span(a, false, &alo, &ahi);
+    span(b, false, &blo, &bhi);
+    if (alo < bhi && blo < ahi)
+        return fail(LOPE_ERR_ALIAS, "%s and %s interiors overlap (double buffering needs two buffers)", an, bn);
+    return LOPE_OK;
+}
+
+int check_stencil(const lope_stencil* st, int ndim, int* ntaps_out) {
+    if (!st) return fail(LOPE_ERR_INVALID_ARG, "null stencil");
+    if (st->ndim != ndim) return fail(LOPE_ERR_INVALID_ARG, "stencil ndim %d != grid ndim %d", st->ndim, ndim);
+    if (st->radius < 0 || st->radius > LOPE_MAX_RADIUS)
+        return fail(LOPE_ERR_INVALID_ARG, "stencil radius %d not in 0..%d", st->radius, LOPE_MAX_RADIUS);
+    if (!st->coeffs) return fail(LOPE_ERR_INVALID_ARG, "null coefficient table");
+    int w = 2 * st->radius + 1, count = 1, nz = 0;
+    for (int a = 0; a < ndim; ++a) count *= w;
+    for (int i = 0; i < count; ++i)
+        if (st->coeffs[i] != 0.0) ++nz;
+    if (nz > LOPE_MAX_TAPS)
+        return fail(LOPE_ERR_UNSUPPORTED, "%d non-zero taps exceed the limit of %d", nz, LOPE_MAX_TAPS);
+    if (ntaps_out) *ntaps_out = nz;
+    return LOPE_OK;
+}
+
+// ---- device checks ----
+int device_ready() {
+    const char* f = getenv("LOPE_FORCE_NO_DEVICE");
+    if (f && f[0] == '1') return fail(LOPE_ERR_NO_DEVICE, "no device (LOPE_FORCE_NO_DEVICE=1)");
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(LOPE_ERR_NO_DEVICE, "no HIP device available");
+    }
+    return LOPE_OK;
+}
+
+// The whole padded box must be device memory inside one allocation, on the
+// current device.
+int check_memory(const lope_grid* g, const char* name) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, g->origin);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LOPE_ERR_INVALID_ARG, "%s: origin is not a HIP allocation (%s)", name, hipGetErrorString(e));
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: origin is not device memory", name);
+    int dev = -1;
+    if (hipGetDevice(&dev) == hipSuccess && attr.device != dev)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: memory is on device %d, current device is %d", name, attr.device, dev);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)g->origin);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LOPE_ERR_INVALID_ARG, "%s: cannot query allocation range (%s)", name, hipGetErrorString(e));
+    }
+    uintptr_t lo, hi;
+    span(g, true, &lo, &hi);
+    const uintptr_t b = (uintptr_t)base;
+    if (lo < b || hi > b + size)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: padded box [%p, %p) lies outside its allocation [%p, %p)", name,
+                    (void*)lo, (void*)hi, (void*)b, (void*)(b + size));
+    return LOPE_OK;
+}
+
+DevGrid dev_grid(const lope_grid* g) {
+    DevGrid d;
+    d.origin = g->origin;
+    d.sy = g->ndim >= 2 ? g->stride[1] : 0;
+    d.sz = g->ndim >= 3 ? g->stride[2] : 0;
+    d.nx = (int32_t)g->n[0];
+    d.ny = (int32_t)g->n[1];
+    d.nz = (int32_t)g->n[2];
+    d.pad = 0;
+    return d;
+}
+
+DevRule dev_rule(const lope_bc* bc, int ndim, bool zero_value) {
+    DevRule r;
+    for (int a = 0; a < 3; ++a) r.per[a] = (a < ndim) ? (bc->kind[a] == LOPE_BC_PERIODIC) : 1;
+    r.pad = 0;
+    r.g = zero_value ? 0.0 : bc->value;
+    return r;
+}
+
+double round_to(double v, int dtype) { return dtype == LOPE_F32 ? (double)(float)v : v; }
+
+// Build the job: coefficients rounded once to the grid dtype, taps in
+// lexicographic order, optionally reflected (adjoint: c'_o = c_{-o}).
+void build_job(SweepJob& j, const lope_grid* src, const lope_grid* dst, const lope_stencil* st,
+               const lope_bc* bc, bool reflect) {
+    j.ndim = src->ndim;
+    j.radius = st->radius;
+    j.dtype = src->dtype;
+    j.src = dev_grid(src);
+    j.dst = dev_grid(dst);
+    j.rule = dev_rule(bc, src->ndim, reflect);
+    const int r = st->radius, w = 2 * r + 1;
+    const int wy = src->ndim >= 2 ? w : 1, wz = src->ndim >= 3 ? w : 1;
+    memset(j.dense, 0, sizeof j.dense);
+    j.ntaps = 0;
+    j.star = true;
+    for (int iz = 0; iz < wz; ++iz)
+        for (int iy = 0; iy < wy; ++iy)
+            for (int ix = 0; ix < w; ++ix) {
+                const int ox = ix - r, oy = src->ndim >= 2 ? iy - r : 0, oz = src->ndim >= 3 ? iz - r : 0;
+                // the coefficient used at offset o: c_o, or c_{-o} when reflected
+                const int sx = reflect ? -ox : ox, sy = reflect ? -oy : oy, sz = reflect ? -oz : oz;
+                const int src_idx = (sx + r) + (src->ndim >= 2 ? (sy + r) * w : 0) +
+                                    (src->ndim >= 3 ? (sz + r) * w * w : 0);
+                const double c = round_to(st->coeffs[src_idx], src->dtype);
+                const int idx = ix + iy * w + iz * w * w;
+                j.dense[idx] = c;
+                if (c != 0.0) {
+                    j.off[j.ntaps][0] = (int8_t)ox;
+                    j.off[j.ntaps][1] = (int8_t)oy;
+                    j.off[j.ntaps][2] = (int8_t)oz;
+                    j.c[j.ntaps] = c;
+                    ++j.ntaps;
+                    if ((ox != 0) + (oy != 0) + (oz != 0) > 1) j.star = false;
+                }
+            }
+}
+
+// ---- variant table and tuning ----
+struct Registry {
+    std::vector<Variant> v;
+    Registry() {
+        const Variant* p;
+        int n = star3d_variants(&p);
+        for (int i = 0; i < n; ++i) v.push_back(p[i]);
+        n = plane2d_variants(&p);
+        for (int i = 0; i < n; ++i) v.push_back(p[i]);
+    }
+};
+Registry& registry() {
+    static Registry r;
+    return r;
+}
+
+struct TuneChoice {
+    int variant, tdepth, chunk;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, TuneChoice> g_tune;
+
+std::tuple<int, int, int, int, int> tune_key(int ndim, int radius, int dtype, bool star, int64_t points) {
+    int bucket = 0;
+    while (bucket < 62 && ((int64_t)1 << (bucket + 1)) <= points) ++bucket;
+    return std::make_tuple(ndim, radius, dtype, star ? 1 : 0, bucket);
+}
+
+bool variant_fits(const Variant& v, const SweepJob& j, int tdepth) {
+    if (v.ndim != j.ndim || v.radius != j.radius || v.dtype != j.dtype || v.tdepth != tdepth) return false;
+    if (v.family == FAM_STAR3D) return j.star;
+    if (v.family == FAM_PLANE2D) return v.box ? true : j.star;
+    return false;
+}
+
+// Default variant for a (job, depth): the first fitting entry in table order
+// (each table lists its preferred tile first); a 2D star stencil prefers a
+// star-shaped kernel when one fits.
+int default_variant(const SweepJob& j, int tdepth) {
+    auto& R = registry().v;
+    int first = 0;
+    for (size_t i = 0; i < R.size(); ++i) {
+        if (!variant_fits(R[i], j, tdepth)) continue;
+        const bool plane_star_job = R[i].family == FAM_PLANE2D && j.star;
+        if (plane_star_job && !R[i].box) return (int)i + 1;
+        if (!first) first = (int)i + 1;
+        if (!plane_star_job) return first;
+    }
+    return first;
+}
+
+// One pass of `depth` sweeps from job.src to job.dst with variant id (0 = generic, depth 1).
+int run_pass(const SweepJob& j, int variant, int chunk, hipStream_t s) {
+    hipError_t e;
+    if (variant <= 0) {
+        e = launch_generic(j, s);
+    } else {
+        const Variant& v = registry().v[variant - 1];
+        e = v.fn(j, chunk > 0 ? chunk : v.default_chunk, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return LOPE_OK;
+}
+
+struct Plan {
+    int variant;  // 0 = generic
+    int tdepth;
+    int chunk;
+};
+
+Plan choose(const SweepJob& j, int tdepth_req, int variant_req, int chunk_req) {
+    Plan p{0, 1, chunk_req};
+    if (variant_req == LOPE_VARIANT_GENERIC) return p;
+    if (variant_req > 0) {
+        const Variant& v = registry().v[variant_req - 1];
+        p.variant = variant_req;
+        p.tdepth = v.tdepth;
+        return p;
+    }
+    int td = tdepth_req;
+    if (td <= 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const int64_t pts = (int64_t)j.src.nx * j.src.ny * j.src.nz;
+        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts));
+        if (it != g_tune.end()) {
+            p.variant = it->second.variant;
+            p.tdepth = it->second.tdepth;
+            if (p.chunk <= 0) p.chunk = it->second.chunk;
+            if (p.variant > 0 && variant_fits(registry().v[p.variant - 1], j, p.tdepth)) return p;
+            p.variant = 0;
+            p.tdepth = 1;
+        }
+        td = 1;
+    }
+    for (; td >= 1; --td) {
+        const int v = default_variant(j, td);
+        if (v) {
+            p.variant = v;
+            p.tdepth = td;
+            return p;
+        }
+    }
+    p.variant = 0;
+    p.tdepth = 1;
+    return p;
+}
+
+int iterate_impl(const lope_grid* a, const lope_grid* b, const lope_stencil* st, const lope_bc* bc,
+                 int64_t n_steps, int32_t tdepth, int variant_req, int chunk_req, void* stream,
+                 int32_t* result_index) {
+    if (!result_index) return fail(LOPE_ERR_INVALID_ARG, "null result_index");
+    int rc;
+    if ((rc = check_grid(a, "a")) || (rc = check_grid(b, "b")) || (rc = check_same(a, b, "a", "b")) ||
+        (rc = check_bc(bc, a->ndim)) || (rc = check_stencil(st, a->ndim, nullptr)))
+        return rc;
+    if (n_steps < 0) return fail(LOPE_ERR_INVALID_ARG, "n_steps %lld < 0", (long long)n_steps);
+    if (tdepth < 0 || tdepth > 4) return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 0..4", tdepth);
+    if (st->radius > a->h || st->radius > b->h)
+        return fail(LOPE_ERR_HALO_TOO_SMALL, "stencil radius %d exceeds halo width (a.h=%d, b.h=%d)", st->radius,
+                    a->h, b->h);
+    if ((rc = check_alias(a, b, "a", "b"))) return rc;
+    if (variant_req < LOPE_VARIANT_GENERIC || variant_req > (int)registry().v.size())
+        return fail(LOPE_ERR_INVALID_ARG, "variant %d out of range", variant_req);
+    *result_index = 0;
+    if ((rc = device_ready())) return rc;
+    if ((rc = check_memory(a, "a")) || (rc = check_memory(b, "b"))) return rc;
+    if (is_empty(a) || n_steps == 0) return LOPE_OK;
+
+    static thread_local SweepJob job;
+    build_job(job, a, b, st, bc, false);
+    if (variant_req > 0 && !variant_fits(registry().v[variant_req - 1], job, registry().v[variant_req - 1].tdepth))
+        return fail(LOPE_ERR_UNSUPPORTED, "variant %d does not fit this grid/stencil", variant_req);
+    const Plan plan = choose(job, tdepth, variant_req, chunk_req);
+    const hipStream_t s = (hipStream_t)stream;
+    const DevGrid ga = dev_grid(a), gb = dev_grid(b);
+    int64_t done = 0, passes = 0;
+    while (done < n_steps) {
+        int64_t left = n_steps - done;
+        int depth = plan.tdepth;
+        int variant = plan.variant;
+        if (left < depth && variant > 0) {  // remainder: the best variant of that smaller depth
+            depth = (int)left;
+            variant = default_variant(job, depth);
+            if (!variant) {
+                depth = 1;
+                variant = default_variant(job, 1);
+            }
+        }
+        job.src = (passes & 1) ? gb : ga;
+        job.dst = (passes & 1) ? ga : gb;
+        if ((rc = run_pass(job, variant, variant == plan.variant ? plan.chunk : 0, s))) return rc;
+        done += variant > 0 ? registry().v[variant - 1].tdepth : 1;
+        ++passes;
+    }
+    *result_index = (int32_t)(passes & 1);
+    return LOPE_OK;
+}
+
+
+// ---- batch plans ----
+constexpr int64_t kSlabPoints = 16384;
+
+struct PlanGrid {
+    lope_grid src, dst;
+    lope_bc bc;
+    std::vector<double> coeffs;
+    lope_stencil st;
+};
+
+}  // namespace
+
+struct lope_batch_plan {
+    int dtype = LOPE_F32;
+    int64_t n_steps = 0;
+    int nslabs = 0;
+    int nwg = 0;
+    int device = 0;
+    std::vector<PlanGrid> grids;
+    std::vector<SweepJob> jobs;       // per-grid launches (the comparison path)
+    std::vector<int> job_variant;
+    BatchGrid* d_grids = nullptr;
+    BatchSlab* d_slabs = nullptr;
+    BatchQueue* d_queues = nullptr;
+    int* d_done = nullptr;
+    unsigned long long* d_heads = nullptr;
+    int* d_err = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void plan_free(lope_batch_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_grids) (void)hipFree(p->d_grids);
+    if (p->d_slabs) (void)hipFree(p->d_slabs);
+    if (p->d_queues) (void)hipFree(p->d_queues);
+    if (p->d_done) (void)hipFree(p->d_done);
+    if (p->d_heads) (void)hipFree(p->d_heads);
+    if (p->d_err) (void)hipFree(p->d_err);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lope_get_device(int ordinal, int* out) {
+    if (!out) return fail(LOPE_ERR_INVALID_ARG, "null output pointer");
+    *out = LOPE_HOST;
+    const char* f = getenv("LOPE_FORCE_NO_DEVICE");
+    if (f && f[0] == '1') return LOPE_OK;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        return LOPE_OK;
+    }
+    if (ordinal >= 0 && ordinal < n) *out = ordinal;
+    return LOPE_OK;
+}
+
+int lope_halo_fill(const lope_grid* g, const lope_bc* bc, void* stream) {
+    int rc;
+    if ((rc = check_grid(g, "grid")) || (rc = check_bc(bc, g->ndim))) return rc;
+    if ((rc = device_ready())) return rc;
+    if ((rc = check_memory(g, "grid"))) return rc;
+    if (is_empty(g) || g->h == 0) return LOPE_OK;
+    const hipError_t e = launch_halo_fill(dev_grid(g), g->ndim, g->h, g->dtype, dev_rule(bc, g->ndim, false),
+                                          (hipStream_t)stream);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "halo fill launch");
+}
+
+int lope_apply(const lope_grid* src, const lope_grid* dst, const lope_stencil* st, const lope_bc* bc,
+               void* stream) {
+    int32_t idx = 0;
+    return iterate_impl(src, dst, st, bc, 1, 1, 0, 0, stream, &idx);
+}
+
+int lope_iterate(const lope_grid* a, const lope_grid* b, const lope_stencil* st, const lope_bc* bc,
+                 int64_t n_steps, int32_t tdepth, void* stream, int32_t* result_index) {
+    return iterate_impl(a, b, st, bc, n_steps, tdepth, 0, 0, stream, result_index);
+}
+
+int lope_iterate_tuned(const lope_grid* a, const lope_grid* b, const lope_stencil* st, const lope_bc* bc,
+                       int64_t n_steps, const lope_tuning* tune, void* stream, int32_t* result_index) {
+    if (!tune) return fail(LOPE_ERR_INVALID_ARG, "null tuning");
+    if (tune->chunk < 0) return fail(LOPE_ERR_INVALID_ARG, "chunk %d < 0", tune->chunk);
+    return iterate_impl(a, b, st, bc, n_steps, tune->tdepth, tune->variant, tune->chunk, stream, result_index);
+}
+
+int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_stencil* st, const lope_bc* bc,
+                       double* gbar_dirichlet, void* stream) {
+    int rc;
+    if ((rc = check_grid(ybar, "ybar")) || (rc = check_grid(xbar, "xbar")) ||
+        (rc = check_same(ybar, xbar, "ybar", "xbar")) || (rc = check_bc(bc, ybar->ndim)) ||
+        (rc = check_stencil(st, ybar->ndim, nullptr)))
+        return rc;
+    if (st->radius > ybar->h)
+        return fail(LOPE_ERR_HALO_TOO_SMALL, "stencil radius %d exceeds halo width %d", st->radius, ybar->h);
+    if ((rc = check_alias(ybar, xbar, "ybar", "xbar"))) return rc;
+    if ((rc = device_ready())) return rc;
+    if ((rc = check_memory(ybar, "ybar")) || (rc = check_memory(xbar, "xbar"))) return rc;
+    if (gbar_dirichlet) {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, gbar_dirichlet) != hipSuccess ||
+            (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+            (void)hipGetLastError();
+            return fail(LOPE_ERR_INVALID_ARG, "gbar_dirichlet must be a device pointer");
+        }
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    static thread_local SweepJob job;
+    if (is_empty(ybar)) {
+        if (gbar_dirichlet) {
+            build_job(job, ybar, xbar, st, bc, false);
+            job.src.nx = 0;
+            const hipError_t e = launch_gbar(job, gbar_dirichlet, s);
+            if (e != hipSuccess) return hip_fail(e, "gbar launch");
+        }
+        return LOPE_OK;
+    }
+    if (gbar_dirichlet) {
+        build_job(job, ybar, xbar, st, bc, false);
+        const hipError_t e = launch_gbar(job, gbar_dirichlet, s);
+        if (e != hipSuccess) return hip_fail(e, "gbar launch");
+    }
+    build_job(job, ybar, xbar, st, bc, true);
+    const Plan plan = choose(job, 1, 0, 0);
+    return run_pass(job, plan.tdepth == 1 ? plan.variant : 0, plan.chunk, s);
+}
+
+int lope_apply_var(const lope_grid* src, const lope_grid* dst, const lope_varcoef* vc, const lope_bc* bc,
+                   void* stream) {
+    int rc;
+    if (!vc) return fail(LOPE_ERR_INVALID_ARG, "null varcoef");
+    if ((rc = check_grid(src, "src")) || (rc = check_grid(dst, "dst")) || (rc = check_grid(vc->kappa, "kappa")) ||
+        (rc = check_same(src, dst, "src", "dst")) || (rc = check_same(src, vc->kappa, "src", "kappa")) ||
+        (rc = check_bc(bc, src->ndim)))
+        return rc;
+    if (src->ndim != 3) return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion is 3D only");
+    for (int a = 0; a < 3; ++a)
+        if (bc->kind[a] != LOPE_BC_PERIODIC)
+            return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion supports periodic boundaries only");
+    if (src->h < 1 || vc->kappa->h < 1) return fail(LOPE_ERR_HALO_TOO_SMALL, "src and kappa need h >= 1");
+    if ((rc = check_alias(src, dst, "src", "dst")) || (rc = check_alias(vc->kappa, dst, "kappa", "dst"))) return rc;
+    if ((rc = device_ready())) return rc;
+    if ((rc = check_memory(src, "src")) || (rc = check_memory(dst, "dst")) || (rc = check_memory(vc->kappa, "kappa")))
+        return rc;
+    if (is_empty(src)) return LOPE_OK;
+    const hipError_t e = launch_var_forward(dev_grid(src), dev_grid(dst), dev_grid(vc->kappa), src->dtype, vc->dt,
+                                            (hipStream_t)stream);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion launch");
+}
+
+int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, const lope_grid* u_t,
+                           const lope_varcoef* vc, const lope_bc* bc, const lope_grid* gkappa, void* stream) {
+    int rc;
+    if (!vc) return fail(LOPE_ERR_INVALID_ARG, "null varcoef");
+    if ((rc = check_grid(lam_next, "lam_next")) || (rc = check_grid(lam, "lam")) || (rc = check_grid(u_t, "u_t")) ||
+        (rc = check_grid(vc->kappa, "kappa")) || (rc = check_grid(gkappa, "gkappa")) ||
+        (rc = check_same(lam_next, lam, "lam_next", "lam")) || (rc = check_same(lam_next, u_t, "lam_next", "u_t")) ||
+        (rc = check_same(lam_next, vc->kappa, "lam_next", "kappa")) || (rc = check_bc(bc, lam_next->ndim)))
+        return rc;
+    if (gkappa->ndim != lam_next->ndim || gkappa->n[0] != lam_next->n[0] || gkappa->n[1] != lam_next->n[1] ||
+        gkappa->n[2] != lam_next->n[2])
+        return fail(LOPE_ERR_INVALID_ARG, "gkappa extents differ");
+    if (lam_next->ndim != 3) return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion is 3D only");
+    for (int a = 0; a < 3; ++a)
+        if (bc->kind[a] != LOPE_BC_PERIODIC)
+            return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion supports periodic boundaries only");
+    if (lam_next->h < 1 || u_t->h < 1 || vc->kappa->h < 1)
+        return fail(LOPE_ERR_HALO_TOO_SMALL, "lam_next, u_t and kappa need h >= 1");
+    if ((rc = check_alias(lam_next, lam, "lam_next", "lam")) || (rc = check_alias(u_t, lam, "u_t", "lam")) ||
+        (rc = check_alias(vc->kappa, lam, "kappa", "lam")) || (rc = check_alias(gkappa, lam, "gkappa", "lam")) ||
+        (rc = check_alias(gkappa, lam_next, "gkappa", "lam_next")) || (rc = check_alias(gkappa, u_t, "gkappa", "u_t")) ||
+        (rc = check_alias(gkappa, vc->kappa, "gkappa", "kappa")))
+        return rc;
+    if ((rc = device_ready())) return rc;
+    if ((rc = check_memory(lam_next, "lam_next")) || (rc = check_memory(lam, "lam")) ||
+        (rc = check_memory(u_t, "u_t")) || (rc = check_memory(vc->kappa, "kappa")) ||
+        (rc = check_memory(gkappa, "gkappa")))
+        return rc;
+    if (is_empty(lam_next)) return LOPE_OK;
+    const hipError_t e =
+        launch_var_adjoint(dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(vc->kappa), dev_grid(gkappa),
+                           lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion adjoint launch");
+}
+
+int lope_accumulate(const lope_grid* partial, const lope_grid* total, void* stream) {
+    int rc;
+    if ((rc = check_grid(partial, "partial")) || (rc = check_grid(total, "total"))) return rc;
+    if (total->dtype != LOPE_F64) return fail(LOPE_ERR_INVALID_ARG, "total must be F64");
+    if (partial->ndim != total->ndim || partial->n[0] != total->n[0] || partial->n[1] != total->n[1] ||
+        partial->n[2] != total->n[2])
+        return fail(LOPE_ERR_INVALID_ARG, "partial and total extents differ");
+    if ((rc = check_alias(partial, total, "partial", "total"))) return rc;
+    if ((rc = device_ready())) return rc;
+    if ((rc = check_memory(partial, "partial")) || (rc = check_memory(total, "total"))) return rc;
+    if (is_empty(partial)) return LOPE_OK;
+    const hipError_t e = launch_accumulate(dev_grid(partial), partial->dtype, dev_grid(total), (hipStream_t)stream);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "accumulate launch");
+}
+
+
+int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_t n_steps, void* stream,
+                           lope_batch_plan** out) {
+    int rc;
+    if (!out) return fail(LOPE_ERR_INVALID_ARG, "null plan output");
+    *out = nullptr;
+    if (!items && n_items > 0) return fail(LOPE_ERR_INVALID_ARG, "null item array");
+    if (n_items < 0 || n_items > (1 << 20)) return fail(LOPE_ERR_INVALID_ARG, "n_items %lld out of range", (long long)n_items);
+    if (n_steps < 0 || n_steps > (1 << 24)) return fail(LOPE_ERR_INVALID_ARG, "n_steps %lld out of range", (long long)n_steps);
+    int dtype = n_items > 0 ? items[0].src.dtype : LOPE_F32;
+    for (int64_t i = 0; i < n_items; ++i) {
+        const lope_batch_item& it = items[i];
+        char a[32], b[32];
+        snprintf(a, sizeof a, "items[%lld].src", (long long)i);
+        snprintf(b, sizeof b, "items[%lld].dst", (long long)i);
+        if ((rc = check_grid(&it.src, a)) || (rc = check_grid(&it.dst, b)) || (rc = check_same(&it.src, &it.dst, a, b)) ||
+            (rc = check_bc(&it.bc, it.src.ndim)) || (rc = check_stencil(&it.stencil, it.src.ndim, nullptr)))
+            return rc;
+        if (it.src.ndim != 2) return fail(LOPE_ERR_UNSUPPORTED, "%s: batches hold 2D grids", a);
+        if (it.src.dtype != dtype) return fail(LOPE_ERR_INVALID_ARG, "%s: all grids of a batch share one dtype", a);
+        if (it.stencil.radius > 1) return fail(LOPE_ERR_UNSUPPORTED, "%s: batch stencils have radius <= 1", a);
+        if (it.src.h < 1 || it.dst.h < 1) return fail(LOPE_ERR_HALO_TOO_SMALL, "%s: batch grids need h >= 1", a);
+        const int64_t maxw = dtype == LOPE_F64 ? 1024 : 2048;
+        if (it.src.n[0] > maxw) return fail(LOPE_ERR_UNSUPPORTED, "%s: rows wider than %lld", a, (long long)maxw);
+        if ((rc = check_alias(&it.src, &it.dst, a, b))) return rc;
+    }
+    if ((rc = device_ready())) return rc;
+    for (int64_t i = 0; i < n_items; ++i) {
+        if ((rc = check_memory(&items[i].src, "batch src")) || (rc = check_memory(&items[i].dst, "batch dst"))) return rc;
+    }
+    lope_batch_plan* p = new lope_batch_plan();
+    p->dtype = dtype;
+    p->n_steps = n_steps;
+    (void)hipGetDevice(&p->device);
+    // copy items (the stencil table is copied; grids are borrowed)
+    p->grids.resize((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) {
+        PlanGrid& g = p->grids[(size_t)i];
+        g.src = items[i].src;
+        g.dst = items[i].dst;
+        g.bc = items[i].bc;
+        const int r = items[i].stencil.radius, w = 2 * r + 1;
+        g.coeffs.assign(items[i].stencil.coeffs, items[i].stencil.coeffs + w * w);
+        g.st = items[i].stencil;
+        g.st.coeffs = g.coeffs.data();
+    }
+    // per-grid jobs for the one-launch-per-grid path
+    p->jobs.resize((size_t)n_items);
+    p->job_variant.resize((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) {
+        PlanGrid& g = p->grids[(size_t)i];
+        build_job(p->jobs[(size_t)i], &g.src, &g.dst, &g.st, &g.bc, false);
+        p->job_variant[(size_t)i] = default_variant(p->jobs[(size_t)i], 1);
+    }
+    // queues: grids dealt to XCD queues by largest-first, least-loaded
+    std::vector<int64_t> order((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
+    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        return items[x].src.n[0] * items[x].src.n[1] > items[y].src.n[0] * items[y].src.n[1];
+    });
+    std::vector<std::vector<int64_t>> qgrids(kNumXcd);
+    std::vector<int64_t> load(kNumXcd, 0);
+    for (int64_t i : order) {
+        int best = 0;
+        for (int q = 1; q < kNumXcd; ++q)
+            if (load[q] < load[best]) best = q;
+        qgrids[best].push_back(i);
+        load[best] += items[i].src.n[0] * items[i].src.n[1];
+    }
+    std::vector<BatchGrid> hg((size_t)n_items);
+    std::vector<BatchSlab> hs;
+    std::vector<BatchQueue> hq(kNumXcd);
+    for (int q = 0; q < kNumXcd; ++q) {
+        hq[q].first_slab = (int32_t)hs.size();
+        for (int64_t i : qgrids[q]) {
+            const PlanGrid& g = p->grids[(size_t)i];
+            const SweepJob& j = p->jobs[(size_t)i];
+            BatchGrid& b = hg[(size_t)i];
+            b.src = dev_grid(&g.src);
+            b.dst = dev_grid(&g.dst);
+            b.rule = dev_rule(&g.bc, 2, false);
+            for (int t = 0; t < 9; ++t) b.c[t] = 0.0;
+            const int r = g.st.radius;
+            for (int oy = -r; oy <= r; ++oy)
+                for (int ox = -r; ox <= r; ++ox) b.c[(ox + 1) + (oy + 1) * 3] = j.dense[(ox + r) + (oy + r) * (2 * r + 1)];
+            b.box = j.star ? 0 : 1;
+            const int64_t nx = g.src.n[0], ny = g.src.n[1];
+            int64_t rows = (kSlabPoints + nx - 1) / (nx > 0 ? nx : 1);
+            if (rows < 4) rows = 4;
+            if (rows > ny) rows = ny;
+            if (rows < 1) rows = 1;
+            const int64_t ns = (nx == 0 || ny == 0) ? 0 : (ny + rows - 1) / rows;
+            b.slab0 = (int32_t)hs.size();
+            b.nslabs = (int32_t)ns;
+            b.rows = (int32_t)rows;
+            const bool pery = g.bc.kind[1] == LOPE_BC_PERIODIC;
+            for (int64_t k = 0; k < ns; ++k) {
+                BatchSlab sl;
+                sl.grid = (int32_t)i;
+                sl.y0 = (int32_t)(k * rows);
+                sl.y1 = (int32_t)std::min(ny, (k + 1) * rows);
+                sl.up = (k > 0) ? (int32_t)(b.slab0 + k - 1) : (pery && ns > 1 ? (int32_t)(b.slab0 + ns - 1) : -1);
+                sl.down = (k + 1 < ns) ? (int32_t)(b.slab0 + k + 1) : (pery && ns > 1 ? (int32_t)b.slab0 : -1);
+                sl.pad = 0;
+                hs.push_back(sl);
+            }
+        }
+        hq[q].nslabs = (int32_t)hs.size() - hq[q].first_slab;
+        hq[q].nitems = (int64_t)hq[q].nslabs * n_steps;
+    }
+    p->nslabs = (int)hs.size();
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (cus <= 0) cus = 256;
+    int nwg = cus * batch_occupancy(dtype);
+    nwg = (nwg / kNumXcd) * kNumXcd;
+    if (nwg < kNumXcd) nwg = kNumXcd;
+    p->nwg = nwg;
+    hipError_t e = hipSuccess;
+    const size_t ns = hs.empty() ? 1 : hs.size();
+    const size_t ng = hg.empty() ? 1 : hg.size();
+    if ((e = hipMalloc(&p->d_grids, ng * sizeof(BatchGrid))) != hipSuccess ||
+        (e = hipMalloc(&p->d_slabs, ns * sizeof(BatchSlab))) != hipSuccess ||
+        (e = hipMalloc(&p->d_queues, kNumXcd * sizeof(BatchQueue))) != hipSuccess ||
+        (e = hipMalloc(&p->d_done, ns * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&p->d_heads, kNumXcd * sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMalloc(&p->d_err, sizeof(int))) != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "batch plan allocation");
+    }
+    if ((!hg.empty() && (e = hipMemcpy(p->d_grids, hg.data(), hg.size() * sizeof(BatchGrid), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!hs.empty() && (e = hipMemcpy(p->d_slabs, hs.data(), hs.size() * sizeof(BatchSlab), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (e = hipMemcpy(p->d_queues, hq.data(), kNumXcd * sizeof(BatchQueue), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(p->d_err, 0, sizeof(int))) != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "batch plan upload");
+    }
+    // capture [counter reset, persistent sweep] into a graph on a private stream
+    hipStream_t cs = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "capture stream");
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_batch(p->d_grids, p->d_slabs, p->d_queues, p->d_done, p->nslabs, p->d_heads, p->d_err,
+                                     (int)n_steps, dtype, p->nwg, cs);
+        e = hipStreamEndCapture(cs, &p->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "batch graph capture");
+    }
+    (void)stream;
+    *out = p;
+    return LOPE_OK;
+}
+
+int lope_batch_apply(lope_batch_plan* plan, void* stream) {
+    if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
+    int rc;
+    if ((rc = device_ready())) return rc;
+    if (plan->grids.empty() || plan->n_steps == 0) return LOPE_OK;
+    const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "batch graph launch");
+}
+
+int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream) {
+    if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
+    int rc;
+    if ((rc = device_ready())) return rc;
+    const hipStream_t s = (hipStream_t)stream;
+    for (size_t i = 0; i < plan->jobs.size(); ++i) {
+        SweepJob& j = plan->jobs[i];
+        if (j.src.nx == 0 || j.src.ny == 0) continue;
+        const DevGrid a = dev_grid(&plan->grids[i].src), b = dev_grid(&plan->grids[i].dst);
+        for (int64_t t = 0; t < plan->n_steps; ++t) {
+            j.src = (t & 1) ? b : a;
+            j.dst = (t & 1) ? a : b;
+            if ((rc = run_pass(j, plan->job_variant[i], 0, s))) return rc;
+        }
+        j.src = a;
+        j.dst = b;
+    }
+    return LOPE_OK;
+}
+
+int lope_batch_plan_error(lope_batch_plan* plan, void* stream, int* out) {
+    if (!plan || !out) return fail(LOPE_ERR_INVALID_ARG, "null plan or output");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "stream sync");
+    int v = 0;
+    e = hipMemcpy(&v, plan->d_err, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "error flag read");
+    *out = v;
+    return LOPE_OK;
+}
+
+int lope_batch_plan_destroy(lope_batch_plan* plan) {
+    plan_free(plan);
+    return LOPE_OK;
+}
+
+const char* lope_status_string(int status) {
+    switch (status) {
+        case LOPE_OK: return "ok";
+        case LOPE_ERR_INVALID_ARG: return "invalid argument";
+        case LOPE_ERR_HALO_TOO_SMALL: return "halo too small for stencil radius";
+        case LOPE_ERR_ALIAS: return "source and destination overlap";
+        case LOPE_ERR_UNSUPPORTED: return "unsupported";
+        case LOPE_ERR_NO_DEVICE: return "no device";
+        case LOPE_ERR_HIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char* lope_last_error(void) { return g_last_error.c_str(); }
+
+int lope_variant_count(void) { return (int)registry().v.size(); }
+
+int lope_variant_info(int id, char* text, int cap) {
+    if (id < 1 || id > (int)registry().v.size()) return fail(LOPE_ERR_INVALID_ARG, "variant %d out of range", id);
+    if (!text || cap <= 0) return fail(LOPE_ERR_INVALID_ARG, "null text buffer");
+    const Variant& v = registry().v[id - 1];
+    snprintf(text, (size_t)cap, "%s ndim=%d radius=%d tdepth=%d dtype=%s shape=%s tile=%dx%d nt=%d chunk=%d", v.name,
+             v.ndim, v.radius, v.tdepth, v.dtype == LOPE_F64 ? "f64" : "f32",
+             v.family == FAM_STAR3D ? "star" : (v.box ? "box" : "star"), v.bx, v.by, v.nt, v.default_chunk);
+    return LOPE_OK;
+}
+
+int lope_select_variant(const lope_grid* g, const lope_stencil* st, int32_t tdepth) {
+    int rc;
+    if ((rc = check_grid(g, "grid")) || (rc = check_stencil(st, g->ndim, nullptr))) return rc;
+    if (tdepth < 0 || tdepth > 4) return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 0..4", tdepth);
+    static thread_local SweepJob job;
+    lope_bc bc{};
+    for (int a = 0; a < 3; ++a) bc.kind[a] = LOPE_BC_PERIODIC;
+    build_job(job, g, g, st, &bc, false);
+    return choose(job, tdepth, 0, 0).variant;
+}
+
+int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning* tune) {
+    int rc;
+    if (!tune) return fail(LOPE_ERR_INVALID_ARG, "null tuning");
+    if ((rc = check_grid(g, "grid")) || (rc = check_stencil(st, g->ndim, nullptr))) return rc;
+    if (tune->variant < 0 || tune->variant > (int)registry().v.size())
+        return fail(LOPE_ERR_INVALID_ARG, "variant %d out of range", tune->variant);
+    static thread_local SweepJob job;
+    lope_bc bc{};
+    for (int a = 0; a < 3; ++a) bc.kind[a] = LOPE_BC_PERIODIC;
+    build_job(job, g, g, st, &bc, false);
+    int td = tune->variant > 0 ? registry().v[tune->variant - 1].tdepth : 1;
+    if (tune->variant > 0 && !variant_fits(registry().v[tune->variant - 1], job, td))
+        return fail(LOPE_ERR_UNSUPPORTED, "variant %d does not fit this grid/stencil", tune->variant);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(job.ndim, job.radius, job.dtype, job.star, (int64_t)job.src.nx * job.src.ny * job.src.nz)] =
+        TuneChoice{tune->variant, td, tune->chunk};
+    return LOPE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lope.h"
+
+namespace lope {
+
+constexpr int kMaxTaps = LOPE_MAX_TAPS;
+constexpr int kMaxR = LOPE_MAX_RADIUS;
+constexpr int kNumXcd = 8;   // MI355X: workgroups are dealt round-robin over 8 XCDs
+
+// Interior view of a padded grid (strides in elements; unused axes have n = 1).
+struct DevGrid {
+    void* origin;
+    int64_t sy, sz;
+    int32_t nx, ny, nz;
+    int32_t pad;
+};
+
+// Boundary rule per paper axis: per[a] = 1 periodic, 0 Dirichlet.
+struct DevRule {
+    int32_t per[3];
+    int32_t pad;
+    double g;
+};
+
+// Non-zero taps in lexicographic offset order (x fastest) for the generic kernel.
+template <typename T>
+struct TapList {
+    int32_t n;
+    int32_t pad;
+    int8_t off[kMaxTaps][3];
+    T c[kMaxTaps];
+};
+
+// Everything a sweep launcher needs, fully validated by the ABI layer.
+struct SweepJob {
+    int ndim, radius, dtype;
+    bool star;                      // only axis-aligned taps are non-zero
+    DevGrid src, dst;
+    DevRule rule;
+    int ntaps;
+    int8_t off[kMaxTaps][3];        // non-zero taps, lexicographic order
+    double c[kMaxTaps];             // coefficients rounded to the grid dtype
+    double dense[729];              // full (2r+1)^d table, rounded, x fastest
+};
+
+// ---- launchers (return hipSuccess or the launch error) ----
+hipError_t launch_generic(const SweepJob& j, hipStream_t s);
+hipError_t launch_halo_fill(const DevGrid& g, int ndim, int h, int dtype, const DevRule& rule,
+                            hipStream_t s);
+hipError_t launch_accumulate(const DevGrid& part, int part_dtype, const DevGrid& total,
+                             hipStream_t s);
+hipError_t launch_gbar(const SweepJob& j, double* out, hipStream_t s);
+
+// Tuned kernel families.
+enum Family { FAM_GENERIC = 0, FAM_STAR3D = 1, FAM_PLANE2D = 2 };
+
+typedef hipError_t (*VariantFn)(const SweepJob& j, int chunk, hipStream_t s);
+
+struct Variant {
+    const char* name;
+    int family;
+    int ndim, radius, tdepth, dtype;
+    int box;                        // plane2d: 1 = box taps, 0 = star taps
+    int bx, by, nt;                 // output tile (x, y) and threads per workgroup
+    int default_chunk;
+    VariantFn fn;
+};
+
+// Registries filled by each kernel file.
+int star3d_variants(const Variant** out);
+int plane2d_variants(const Variant** out);
+
+// Variable-coefficient diffusion.
+hipError_t launch_var_forward(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa,
+                              int dtype, double dt, hipStream_t s);
+hipError_t launch_var_adjoint(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u,
+                              const DevGrid& kappa, const DevGrid& gk, int dtype, int gk_dtype,
+                              double dt, hipStream_t s);
+
+// Batched persistent sweeps (tables built by the ABI layer, read by the kernel).
+struct BatchGrid {
+    DevGrid src, dst;
+    DevRule rule;
+    double c[9];          // dense 3x3 table, rounded to the grid dtype, x fastest
+    int32_t box;          // 1: all 9 taps; 0: the 5 star taps
+    int32_t slab0;        // first slab id of this grid
+    int32_t nslabs;
+    int32_t rows;         // rows per slab (the last slab may be shorter)
+};
+
+struct BatchSlab {
+    int32_t grid;
+    int32_t y0, y1;       // rows [y0, y1)
+    int32_t up, down;     // neighbour slab ids (-1: none)
+    int32_t pad;
+};
+
+struct BatchQueue {
+    int32_t first_slab;   // slabs of this queue are [first_slab, first_slab + nslabs)
+    int32_t nslabs;
+    int64_t nitems;       // nslabs * n_steps
+};
+
+hipError_t launch_batch(const BatchGrid* grids, const BatchSlab* slabs, const BatchQueue* queues, int* done,
+                        int nslabs, unsigned long long* heads, int* err, int n_steps, int dtype, int nwg,
+                        hipStream_t s);
+int batch_occupancy(int dtype);
+
+// ---- device helpers ----
+__device__ __forceinline__ int wrap_index(int i, int n) {
+    if ((unsigned)i < (unsigned)n) return i;
+    int m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+// Barrier that orders LDS traffic only: outstanding global loads (prefetches)
+// stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
+// Logical block id from the hardware id so that consecutive logical tiles
+// share an XCD (and its L2): XCD x gets the logical range [x*per, (x+1)*per).
+__device__ __forceinline__ int xcd_logical_block(int nblocks_padded) {
+    const int per = nblocks_padded / kNumXcd;
+    const int b = blockIdx.x;
+    return (b % kNumXcd) * per + b / kNumXcd;
+}
+
+inline int padded_block_count(int nblocks) {
+    return ((nblocks + kNumXcd - 1) / kNumXcd) * kNumXcd;
+}
+
+}  // namespace lope

@@ -1,0 +1,224 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+and structural validation returns the documented codes before any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1502_03504_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lope.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lope_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_functions_parsed():
+    names = declared_functions()
+    assert "lope_apply" in names and "lope_batch_apply" in names and len(names) >= 20
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_exported_symbols_with_nm():
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (lope_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+L = _lib.load()
+
+
+def grid(n=(8, 8, 8), h=1, ndim=3, dtype=_lib.LOPE_F32, origin=0x100000, sy=None, sz=None):
+    g = _lib.lope_grid()
+    g.ndim = ndim
+    g.h = h
+    g.dtype = dtype
+    nn = list(n)[:ndim] + [1] * (3 - ndim)
+    for a in range(3):
+        g.n[a] = nn[a]
+    g.stride[0] = 1
+    g.stride[1] = sy if sy is not None else nn[0] + 2 * h
+    g.stride[2] = sz if sz is not None else g.stride[1] * (nn[1] + 2 * h)
+    g.origin = origin
+    return g
+
+
+def bc(kind=_lib.LOPE_BC_PERIODIC, value=0.0):
+    b = _lib.lope_bc()
+    for a in range(3):
+        b.kind[a] = kind
+    b.value = value
+    return b
+
+
+def stencil(ndim=3, r=1, fill=0.1):
+    arr = np.full((2 * r + 1) ** ndim, fill)
+    s = _lib.lope_stencil()
+    s.ndim = ndim
+    s.radius = r
+    s.coeffs = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return s, arr
+
+
+def far():
+    return 0x40000000
+
+
+def apply(a, b, st, bcv):
+    return L.lope_apply(ctypes.byref(a), ctypes.byref(b), ctypes.byref(st), ctypes.byref(bcv), None)
+
+
+def test_get_device_falls_back_to_host():
+    out = ctypes.c_int(7)
+    assert L.lope_get_device(0, ctypes.byref(out)) == _lib.LOPE_OK
+    assert out.value == _lib.LOPE_HOST
+    assert L.lope_get_device(0, None) == _lib.LOPE_ERR_INVALID_ARG
+
+
+def test_valid_call_without_device_reports_no_device():
+    s, _keep = stencil()
+    assert apply(grid(), grid(origin=far()), s, bc()) == _lib.LOPE_ERR_NO_DEVICE
+    assert b"device" in L.lope_last_error()
+
+
+def test_force_no_device_env():
+    code = ("import ctypes,sys; sys.path.insert(0, %r); from paper_1502_03504_amd import _lib; L=_lib.load(); "
+            "o=ctypes.c_int(5); L.lope_get_device(0, ctypes.byref(o)); print(o.value)" % ROOT)
+    env = dict(os.environ, LOPE_FORCE_NO_DEVICE="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env)
+    assert out.stdout.strip() == "-1"
+
+
+def test_invalid_arguments():
+    s, _keep = stencil()
+    E = _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_apply(None, ctypes.byref(grid()), ctypes.byref(s), ctypes.byref(bc()), None) == E
+    g = grid(ndim=3)
+    g.ndim = 4
+    assert apply(g, grid(origin=far()), s, bc()) == E
+    g = grid()
+    g.dtype = 7
+    assert apply(g, grid(origin=far()), s, bc()) == E
+    g = grid()
+    g.stride[0] = 2
+    assert apply(g, grid(origin=far()), s, bc()) == E
+    assert apply(grid(sy=5), grid(origin=far()), s, bc()) == E            # rows overlap
+    assert apply(grid(sz=10), grid(origin=far()), s, bc()) == E           # planes overlap
+    assert apply(grid(origin=0), grid(origin=far()), s, bc()) == E        # null origin
+    assert apply(grid(n=(8, 8, 9)), grid(origin=far()), s, bc()) == E     # extents differ
+    assert apply(grid(dtype=_lib.LOPE_F64), grid(origin=far()), s, bc()) == E
+    b = bc()
+    b.kind[1] = 5
+    assert apply(grid(), grid(origin=far()), s, b) == E
+    s2, _k2 = stencil(ndim=2)
+    assert apply(grid(), grid(origin=far()), s2, bc()) == E              # stencil ndim
+    g = grid(ndim=2)
+    g.n[2] = 4                                                             # unused axis must be 1
+    assert apply(g, grid(ndim=2, origin=far()), s2, bc()) == E
+    s5, _k5 = stencil(r=5)
+    assert apply(grid(h=5), grid(h=5, origin=far()), s5, bc()) == E       # radius > 4
+    idx = ctypes.c_int32()
+    assert L.lope_iterate(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), ctypes.byref(s),
+                          ctypes.byref(bc()), -1, 0, None, ctypes.byref(idx)) == E
+    assert L.lope_iterate(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), ctypes.byref(s),
+                          ctypes.byref(bc()), 1, 9, None, ctypes.byref(idx)) == E
+    assert L.lope_iterate(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), ctypes.byref(s),
+                          ctypes.byref(bc()), 1, 0, None, None) == E
+
+
+def test_halo_too_small():
+    s, _keep = stencil(r=2)
+    assert apply(grid(h=1), grid(h=2, origin=far()), s, bc()) == _lib.LOPE_ERR_HALO_TOO_SMALL
+    s1, _k = stencil(r=1)
+    assert apply(grid(h=0), grid(h=0, origin=far()), s1, bc()) == _lib.LOPE_ERR_HALO_TOO_SMALL
+
+
+def test_alias_rejected():
+    s, _keep = stencil()
+    a = grid()
+    assert apply(a, grid(), s, bc()) == _lib.LOPE_ERR_ALIAS
+    # interiors overlapping by one plane
+    b = grid(origin=0x100000 + 4 * 7 * 10 * 10)
+    assert apply(a, b, s, bc()) == _lib.LOPE_ERR_ALIAS
+
+
+def test_too_many_taps_unsupported():
+    s, _keep = stencil(ndim=3, r=3, fill=1.0)     # 343 non-zero taps
+    assert apply(grid(h=3), grid(h=3, origin=far()), s, bc()) == _lib.LOPE_ERR_UNSUPPORTED
+
+
+def test_variable_coefficient_restrictions():
+    kap = grid(origin=0x80000000)
+    vc = _lib.lope_varcoef(ctypes.pointer(kap), 0.1)
+    assert L.lope_apply_var(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), ctypes.byref(vc),
+                            ctypes.byref(bc(_lib.LOPE_BC_DIRICHLET)), None) == _lib.LOPE_ERR_UNSUPPORTED
+    k2 = grid(ndim=2, origin=0x80000000)
+    vc2 = _lib.lope_varcoef(ctypes.pointer(k2), 0.1)
+    assert L.lope_apply_var(ctypes.byref(grid(ndim=2)), ctypes.byref(grid(ndim=2, origin=far())), ctypes.byref(vc2),
+                            ctypes.byref(bc()), None) == _lib.LOPE_ERR_UNSUPPORTED
+    assert L.lope_apply_var(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), ctypes.byref(vc),
+                            ctypes.byref(bc()), None) == _lib.LOPE_ERR_NO_DEVICE
+
+
+def test_batch_validation():
+    s2, _k = stencil(ndim=2, r=1)
+    it = (_lib.lope_batch_item * 1)()
+    it[0].src = grid(ndim=2)
+    it[0].dst = grid(ndim=2, origin=far())
+    it[0].stencil = s2
+    it[0].bc = bc()
+    out = ctypes.c_void_p()
+    assert L.lope_batch_plan_create(it, 1, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_NO_DEVICE
+    s3, _k3 = stencil(ndim=2, r=2)
+    it[0].stencil = s3
+    it[0].src = grid(ndim=2, h=2)
+    it[0].dst = grid(ndim=2, h=2, origin=far())
+    assert L.lope_batch_plan_create(it, 1, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_UNSUPPORTED
+    assert L.lope_batch_plan_create(it, 1, 10, None, None) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_plan_destroy(None) == _lib.LOPE_OK
+
+
+def test_status_strings_and_variants():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.lope_status_string(code)
+    n = L.lope_variant_count()
+    assert n > 10
+    buf = ctypes.create_string_buffer(256)
+    assert L.lope_variant_info(1, buf, 256) == 0 and b"ndim=" in buf.value
+    assert L.lope_variant_info(0, buf, 256) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_variant_info(n + 1, buf, 256) == _lib.LOPE_ERR_INVALID_ARG
+
+
+def test_variant_selection_and_tuning_table():
+    s, _keep = stencil(ndim=3, r=1, fill=0.0)
+    arr = _keep
+    arr[13] = 1.0
+    arr[12] = arr[14] = arr[10] = arr[16] = arr[4] = arr[22] = 0.1     # 7-point star
+    g = grid(n=(64, 64, 64))
+    v1 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 1)
+    assert v1 > 0
+    buf = ctypes.create_string_buffer(256)
+    L.lope_variant_info(v1, buf, 256)
+    assert b"star3d" in buf.value and b"tdepth=1" in buf.value
+    v2 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 2)
+    L.lope_variant_info(v2, buf, 256)
+    assert b"tdepth=2" in buf.value
+    t = _lib.lope_tuning(v2, 0, 32, 0)
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(t)) == 0
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0) == v2
+    box, _kb = stencil(ndim=3, r=1, fill=0.1)                            # 3D box: generic kernel
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(box), 1) == 0
