@@ -86,6 +86,8 @@ def halo_fill(u: np.ndarray, h: int, kinds, g: float) -> np.ndarray:
     unchanged and every halo cell set by the boundary rule, g rounded to the
     grid dtype.
     """
+    if u.size == 0:
+        raise ValueError("an empty interior has no halo values to copy")
     gd = float(np.asarray(g, dtype=u.dtype))
     return rule_extend(u, h, kinds, gd).astype(u.dtype)
 
@@ -106,10 +108,15 @@ def _taps(coeffs: np.ndarray, dtype):
 
 
 def sweep(u: np.ndarray, coeffs: np.ndarray, kinds, g: float) -> np.ndarray:
-    """One Jacobi sweep: y[x] = sum_o c_o * B(u)[x+o] over the whole interior."""
+    """One Jacobi sweep: y[x] = sum_o c_o * B(u)[x+o] over the whole interior.
+
+    An empty interior has no element to update and gives an empty result.
+    """
     r = _radius(coeffs)
     if coeffs.ndim != u.ndim:
         raise ValueError("stencil and field dimension differ")
+    if u.size == 0:
+        return np.array(u, copy=True)
     gd = float(np.asarray(g, dtype=u.dtype))
     ext = rule_extend(u, r, kinds, gd)
     y = np.zeros(u.shape, dtype=np.float64)
@@ -190,6 +197,8 @@ def adjoint(ybar: np.ndarray, coeffs: np.ndarray, kinds):
     """
     r = _radius(coeffs)
     d = ybar.ndim
+    if ybar.size == 0:
+        return np.array(ybar, copy=True), 0.0
     yb = ybar.astype(np.float64)
     ext = np.zeros(tuple(n + 2 * r for n in ybar.shape), dtype=np.float64)
     for off, c in _taps(coeffs, ybar.dtype):

@@ -730,8 +730,13 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
+        // bound any single wait to about two seconds of the device's real-time clock
+        int khz = 0;
+        (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device);
+        if (khz <= 0) khz = 100000;
+        const unsigned long long wait_ticks = (unsigned long long)khz * 2000ull;
         hipError_t le = launch_batch(p->d_grids, p->d_slabs, p->d_queues, p->d_done, p->nslabs, p->d_heads, p->d_err,
-                                     (int)n_steps, dtype, p->nwg, cs);
+                                     (int)n_steps, dtype, p->nwg, wait_ticks, cs);
         e = hipStreamEndCapture(cs, &p->graph);
         if (le != hipSuccess) e = le;
     }

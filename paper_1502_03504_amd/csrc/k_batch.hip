@@ -31,7 +31,6 @@
 namespace lope {
 
 constexpr int kBatchThreads = 256;
-constexpr long long kSpinLimit = 1ll << 24;
 
 // Widest padded row held in LDS: nx <= 2048 (float) or 1024 (double).
 template <typename T>
@@ -41,14 +40,15 @@ struct BatchWidth {
 
 namespace {
 
-__device__ __forceinline__ int ld_acquire(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int ld_relaxed(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBatchThreads)
 k_batch(const BatchGrid* __restrict__ grids, const BatchSlab* __restrict__ slabs,
-        const BatchQueue* __restrict__ queues, int* done, unsigned long long* heads, int* err, int n_steps) {
+        const BatchQueue* __restrict__ queues, int* done, unsigned long long* heads, int* err, int n_steps,
+        unsigned long long wait_ticks) {
     __shared__ T ring[4][BatchWidth<T>::value];
     __shared__ long long item_sh;
     __shared__ int ok_sh;
@@ -69,22 +69,26 @@ k_batch(const BatchGrid* __restrict__ grids, const BatchSlab* __restrict__ slabs
         const BatchSlab S = slabs[sid];
         const BatchGrid& Gr = grids[S.grid];
 
-        // wait until this slab and its neighbours finished step s-1
+        // Wait until this slab and its neighbours finished step s-1.  The poll
+        // is a relaxed atomic load (no cache invalidation per poll); one
+        // acquire fence follows once every dependency is met.  The wait is
+        // bounded by the real-time counter, so a broken invariant ends in the
+        // error flag, never in a hang.
         if (tid == 0 && s > 0) {
             const int deps[3] = {sid, S.up, S.down};
-            for (int d = 0; d < 3; ++d) {
+            const unsigned long long t0 = wall_clock64();
+            for (int d = 0; d < 3 && ok_sh; ++d) {
                 if (deps[d] < 0) continue;
-                long long spins = 0;
-                while (ld_acquire(&done[deps[d]]) < s) {
-                    if (++spins > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                while (ld_relaxed(&done[deps[d]]) < s) {
+                    if (wall_clock64() - t0 > wait_ticks || ld_relaxed(err)) {
                         ok_sh = 0;
                         break;
                     }
-                    __builtin_amdgcn_s_sleep(2);
+                    __builtin_amdgcn_s_sleep(8);
                 }
-                if (!ok_sh) break;
             }
-            if (!ok_sh) atomicExch(err, 1);
+            if (ok_sh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            else atomicExch(err, 1);
         }
         __syncthreads();
         if (!ok_sh) break;
@@ -152,8 +156,9 @@ k_batch(const BatchGrid* __restrict__ grids, const BatchSlab* __restrict__ slabs
                 }
             }
         }
-        // publish: every thread's stores are complete, then release the counter
-        __threadfence();
+        // publish: every wave makes its stores visible at agent scope, then one
+        // thread releases the counter
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (tid == 0) __hip_atomic_store(&done[sid], s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -170,15 +175,15 @@ __global__ void k_batch_reset(int* done, int nslabs, unsigned long long* heads, 
 
 hipError_t launch_batch(const BatchGrid* grids, const BatchSlab* slabs, const BatchQueue* queues, int* done,
                         int nslabs, unsigned long long* heads, int* err, int n_steps, int dtype, int nwg,
-                        hipStream_t s) {
+                        unsigned long long wait_ticks, hipStream_t s) {
     const int rb = (nslabs > kNumXcd ? nslabs : kNumXcd);
     hipLaunchKernelGGL(k_batch_reset, dim3((rb + 255) / 256), dim3(256), 0, s, done, nslabs, heads, err);
     if (dtype == LOPE_F32)
         hipLaunchKernelGGL(k_batch<float>, dim3(nwg), dim3(kBatchThreads), 0, s, grids, slabs, queues, done, heads,
-                           err, n_steps);
+                           err, n_steps, wait_ticks);
     else
         hipLaunchKernelGGL(k_batch<double>, dim3(nwg), dim3(kBatchThreads), 0, s, grids, slabs, queues, done, heads,
-                           err, n_steps);
+                           err, n_steps, wait_ticks);
     return hipGetLastError();
 }
 

@@ -108,7 +108,7 @@ struct BatchQueue {
 
 hipError_t launch_batch(const BatchGrid* grids, const BatchSlab* slabs, const BatchQueue* queues, int* done,
                         int nslabs, unsigned long long* heads, int* err, int n_steps, int dtype, int nwg,
-                        hipStream_t s);
+                        unsigned long long wait_ticks, hipStream_t s);
 int batch_occupancy(int dtype);
 
 // ---- device helpers ----

@@ -1,0 +1,74 @@
+"""Gradients of the checkpointed diffusion driver against the oracle and
+central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1502_03504_amd.autograd import diffusion_gradient
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n, steps, seed=0):
+    c = synth.case_diffusion(n=n, steps=steps, seed=seed)
+    t = lambda a: torch.from_numpy(a).cuda()
+    return c, t(c.u0), t(c.kappa), t(c.target)
+
+
+def test_gradient_matches_central_differences_16():
+    c, u0, k, tg = _case(16, 200)
+    loss, gu, gk = diffusion_gradient(u0, k, tg, c.dt, c.steps, c.checkpoint_every)
+    gu, gk = gu.cpu().numpy(), gk.cpu().numpy()
+    u64, k64, t64 = (c.u0.astype(np.float64), c.kappa.astype(np.float64), c.target.astype(np.float64))
+
+    def L(uu, kk):
+        return oracle.diffusion_loss(oracle.diffusion_forward(uu, kk, c.dt, c.steps)[-1], t64)
+
+    rng = np.random.default_rng(1)
+    fd_u, an_u, fd_k, an_k = [], [], [], []
+    for j in rng.choice(u64.size, 24, replace=False):
+        e = np.zeros(u64.size)
+        e[j] = 1e-3
+        e = e.reshape(u64.shape)
+        fd_u.append((L(u64 + e, k64) - L(u64 - e, k64)) / 2e-3)
+        an_u.append(gu.ravel()[j])
+    for j in rng.choice(k64.size, 24, replace=False):
+        e = np.zeros(k64.size)
+        e[j] = 1e-5
+        e = e.reshape(k64.shape)
+        fd_k.append((L(u64, k64 + e) - L(u64, k64 - e)) / 2e-5)
+        an_k.append(gk.ravel()[j])
+    assert rel_err(an_u, fd_u) <= 1e-4, rel_err(an_u, fd_u)
+    assert rel_err(an_k, fd_k) <= 1e-4, rel_err(an_k, fd_k)
+    for _ in range(4):
+        du, dk = rng.standard_normal(u64.shape), rng.standard_normal(k64.shape)
+        eps = 1e-6
+        fd = (L(u64 + eps * du, k64 + eps * dk) - L(u64 - eps * du, k64 - eps * dk)) / (2 * eps)
+        an = float(np.vdot(gu.astype(np.float64), du) + np.vdot(gk.astype(np.float64), dk))
+        assert abs(fd - an) <= 1e-4 * abs(fd), (fd, an)
+
+
+def test_gradient_matches_oracle_adjoint_48():
+    c, u0, k, tg = _case(48, 200, seed=2)
+    loss, gu, gk = diffusion_gradient(u0, k, tg, c.dt, c.steps, c.checkpoint_every)
+    L, wu, wk = oracle.diffusion_gradient(c.u0, c.kappa, c.target, c.dt, c.steps)
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert rel_err(gu.cpu().numpy(), wu) <= 1e-5, rel_err(gu.cpu().numpy(), wu)
+    assert rel_err(gk.cpu().numpy(), wk) <= 1e-4, rel_err(gk.cpu().numpy(), wk)
+
+
+def test_checkpoint_interval_does_not_change_gradient():
+    c, u0, k, tg = _case(24, 60, seed=3)
+    ref = None
+    for every in (1, 7, 20, 60):
+        loss, gu, gk = diffusion_gradient(u0, k, tg, c.dt, c.steps, every)
+        cur = (loss.item(), gu.cpu().numpy(), gk.cpu().numpy())
+        if ref is None:
+            ref = cur
+        else:
+            assert cur[0] == ref[0]
+            np.testing.assert_array_equal(cur[1], ref[1])
+            np.testing.assert_array_equal(cur[2], ref[2])

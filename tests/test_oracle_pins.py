@@ -325,3 +325,27 @@ def test_symmetric_stencil_is_self_adjoint():
 
 def test_result_index():
     assert [oracle.result_index(n) for n in (0, 1, 2, 7, 100)] == [0, 1, 0, 1, 0]
+
+
+def test_empty_interior():
+    st = synth.heat_star(3, 0.1)
+    for shape in [(0, 4, 5), (3, 0, 2), (2, 3, 0)]:
+        u = np.zeros(shape)
+        assert oracle.sweep(u, st.coeffs, (P, D, P), 1.0).shape == shape
+        assert oracle.iterate(u, st.coeffs, (D, D, D), 1.0, 3).shape == shape
+        xb, gb = oracle.adjoint(u, st.coeffs, (D, D, D))
+        assert xb.shape == shape and gb == 0.0
+    with pytest.raises(ValueError):
+        oracle.halo_fill(np.zeros((0, 3)), 1, (D, D), 0.0)
+
+
+def test_extent_one_axes_brute_force():
+    """Extent-1 axes: periodic wrap maps every neighbour onto the one cell."""
+    rng = np.random.default_rng(15)
+    for shape, kinds in [((1, 1, 1), (P, P, P)), ((1, 7, 1), (P, D, P)), ((3, 1, 4), (D, P, D)),
+                         ((1, 1, 1), (D, D, D))]:
+        st = synth.random_stencil(rng, 3, 1, "box")
+        A, b = brute.sweep_operator(shape, st.coeffs, kinds)
+        u = rng.standard_normal(shape)
+        np.testing.assert_allclose(oracle.sweep(u, st.coeffs, kinds, 0.3).ravel(), A @ u.ravel() + 0.3 * b,
+                                   rtol=0, atol=1e-14)
