@@ -207,7 +207,7 @@ int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, cons
 /* total (F64) += partial (F32 or F64) over the interior, then partial = 0. */
 int lope_accumulate(const lope_grid* partial, const lope_grid* total, void* stream);
 
-/* ---- batches: many independent grids in one persistent launch ------------- */
+/* ---- batches: many independent grids advanced together -------------------- */
 
 /* One grid of a batch: a 2D sweep from src to dst (both padded grids),
  * iterated with its own stencil and rule.  The state alternates between src
@@ -215,35 +215,37 @@ int lope_accumulate(const lope_grid* partial, const lope_grid* total, void* stre
 typedef struct lope_batch_item {
     lope_grid src;
     lope_grid dst;
-    lope_stencil stencil;         /* 2D, radius 1; copied at plan creation */
+    lope_stencil stencil;         /* 2D, radius <= 1; copied at plan creation */
     lope_bc bc;
 } lope_batch_item;
 
 typedef struct lope_batch_plan lope_batch_plan;
 
 /* Build a plan for n_items grids and n_steps sweeps each: validates every
- * item, builds the tile work list, uploads it (the plan owns this device
- * memory), and captures the persistent launch into a HIP graph on `stream`.
- * The plan borrows the grids' memory until it is destroyed.  Supports 2D
- * grids with radius-1 stencils of at most 9 taps (else LOPE_ERR_UNSUPPORTED). */
+ * item, cuts every grid into row slabs of about 16K points, and uploads the
+ * grid and slab tables (the plan owns this device memory).  The plan borrows
+ * the grids' memory until it is destroyed.  Supports 2D float32 grids up to
+ * 2048 columns or float64 grids up to 1024 columns, radius <= 1 stencils, one
+ * dtype per batch (else LOPE_ERR_UNSUPPORTED / LOPE_ERR_INVALID_ARG).
+ * `stream` is unused (creation synchronises its uploads). */
 int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_t n_steps,
                            void* stream, lope_batch_plan** out);
 
-/* Launch the plan's graph on `stream`: every grid advances n_steps sweeps;
- * grid i ends in its src if n_steps is even, else in its dst. */
+/* Advance every grid n_steps sweeps with one launch per sweep covering all
+ * slabs of all grids (n_steps launches in total); grid i ends in its src if
+ * n_steps is even, else in its dst. */
 int lope_batch_apply(lope_batch_plan* plan, void* stream);
 
-/* Same work as lope_batch_apply as ordinary kernel launches, one per grid
- * per sweep (the baseline the persistent launch is compared with). */
+/* Same work as lope_batch_apply as ordinary lope_iterate launches, one per
+ * grid per sweep (the baseline the batched launch is compared with). */
 int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream);
 
-/* Synchronise `stream` and report whether the last launch of the plan hit
- * its internal wait bound (a broken scheduling invariant): *out = 0 when all
- * work completed, 1 otherwise.  out must not be NULL. */
+/* Synchronise `stream`; *out = 0 when the plan's work completed.  out must
+ * not be NULL. */
 int lope_batch_plan_error(lope_batch_plan* plan, void* stream, int* out);
 
-/* Release the plan's device memory and graph (waits for nothing: the caller
- * synchronises first if the plan may still be running). NULL is a no-op. */
+/* Release the plan's device memory (the caller synchronises first if the plan
+ * may still be running).  NULL is a no-op. */
 int lope_batch_plan_destroy(lope_batch_plan* plan);
 
 /* ---- introspection --------------------------------------------------------- */

@@ -12,6 +12,7 @@ tensor axis.  Boundary kinds are given per paper axis, x first.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 import torch
@@ -31,6 +32,16 @@ DIRICHLET = "dirichlet"
 PERIODIC = "periodic"
 
 _ALIGN_BYTES = 128
+
+
+def _register_default_tuning():
+    if os.environ.get("LOPE_NO_TUNE_CACHE") == "1":
+        return
+    from .tune import register_cache
+    register_cache()
+
+
+_lib._ON_LOAD.append(_register_default_tuning)
 
 
 def library_path() -> str:

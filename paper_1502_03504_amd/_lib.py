@@ -108,6 +108,7 @@ SIGNATURES = {
 }
 
 _lib = None
+_ON_LOAD = []          # hooks run once after the library is loaded
 
 
 def load() -> ctypes.CDLL:
@@ -123,6 +124,8 @@ def load() -> ctypes.CDLL:
             fn.restype = res
             fn.argtypes = args
         _lib = lib
+        for hook in _ON_LOAD:
+            hook()
     return _lib
 
 

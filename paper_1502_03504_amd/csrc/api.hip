@@ -394,33 +394,22 @@ struct lope_batch_plan {
     int dtype = LOPE_F32;
     int64_t n_steps = 0;
     int nslabs = 0;
-    int nwg = 0;
     int device = 0;
     std::vector<PlanGrid> grids;
     std::vector<SweepJob> jobs;       // per-grid launches (the comparison path)
     std::vector<int> job_variant;
     BatchGrid* d_grids = nullptr;
     BatchSlab* d_slabs = nullptr;
-    BatchQueue* d_queues = nullptr;
-    int* d_done = nullptr;
-    unsigned long long* d_heads = nullptr;
-    int* d_err = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    int* d_order = nullptr;
 };
 
 namespace {
 
 void plan_free(lope_batch_plan* p) {
     if (!p) return;
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->d_grids) (void)hipFree(p->d_grids);
     if (p->d_slabs) (void)hipFree(p->d_slabs);
-    if (p->d_queues) (void)hipFree(p->d_queues);
-    if (p->d_done) (void)hipFree(p->d_done);
-    if (p->d_heads) (void)hipFree(p->d_heads);
-    if (p->d_err) (void)hipFree(p->d_err);
+    if (p->d_order) (void)hipFree(p->d_order);
     delete p;
 }
 
@@ -639,7 +628,9 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         build_job(p->jobs[(size_t)i], &g.src, &g.dst, &g.st, &g.bc, false);
         p->job_variant[(size_t)i] = default_variant(p->jobs[(size_t)i], 1);
     }
-    // queues: grids dealt to XCD queues by largest-first, least-loaded
+    // grids dealt to the 8 XCD ranges largest-first, least-loaded; slabs laid
+    // out grid by grid in that order so a grid's slabs get consecutive
+    // workgroup ids (one XCD range)
     std::vector<int64_t> order((size_t)n_items);
     for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
     std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
@@ -656,9 +647,7 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
     }
     std::vector<BatchGrid> hg((size_t)n_items);
     std::vector<BatchSlab> hs;
-    std::vector<BatchQueue> hq(kNumXcd);
     for (int q = 0; q < kNumXcd; ++q) {
-        hq[q].first_slab = (int32_t)hs.size();
         for (int64_t i : qgrids[q]) {
             const PlanGrid& g = p->grids[(size_t)i];
             const SweepJob& j = p->jobs[(size_t)i];
@@ -680,71 +669,32 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
             b.slab0 = (int32_t)hs.size();
             b.nslabs = (int32_t)ns;
             b.rows = (int32_t)rows;
-            const bool pery = g.bc.kind[1] == LOPE_BC_PERIODIC;
             for (int64_t k = 0; k < ns; ++k) {
-                BatchSlab sl;
+                BatchSlab sl{};
                 sl.grid = (int32_t)i;
                 sl.y0 = (int32_t)(k * rows);
                 sl.y1 = (int32_t)std::min(ny, (k + 1) * rows);
-                sl.up = (k > 0) ? (int32_t)(b.slab0 + k - 1) : (pery && ns > 1 ? (int32_t)(b.slab0 + ns - 1) : -1);
-                sl.down = (k + 1 < ns) ? (int32_t)(b.slab0 + k + 1) : (pery && ns > 1 ? (int32_t)b.slab0 : -1);
-                sl.pad = 0;
                 hs.push_back(sl);
             }
         }
-        hq[q].nslabs = (int32_t)hs.size() - hq[q].first_slab;
-        hq[q].nitems = (int64_t)hq[q].nslabs * n_steps;
     }
     p->nslabs = (int)hs.size();
-    int cus = 0;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
-    if (cus <= 0) cus = 256;
-    int nwg = cus * batch_occupancy(dtype);
-    nwg = (nwg / kNumXcd) * kNumXcd;
-    if (nwg < kNumXcd) nwg = kNumXcd;
-    p->nwg = nwg;
+    std::vector<int> ho(hs.size());
+    for (size_t k = 0; k < hs.size(); ++k) ho[k] = (int)k;
     hipError_t e = hipSuccess;
     const size_t ns = hs.empty() ? 1 : hs.size();
     const size_t ng = hg.empty() ? 1 : hg.size();
     if ((e = hipMalloc(&p->d_grids, ng * sizeof(BatchGrid))) != hipSuccess ||
         (e = hipMalloc(&p->d_slabs, ns * sizeof(BatchSlab))) != hipSuccess ||
-        (e = hipMalloc(&p->d_queues, kNumXcd * sizeof(BatchQueue))) != hipSuccess ||
-        (e = hipMalloc(&p->d_done, ns * sizeof(int))) != hipSuccess ||
-        (e = hipMalloc(&p->d_heads, kNumXcd * sizeof(unsigned long long))) != hipSuccess ||
-        (e = hipMalloc(&p->d_err, sizeof(int))) != hipSuccess) {
+        (e = hipMalloc(&p->d_order, ns * sizeof(int))) != hipSuccess) {
         plan_free(p);
         return hip_fail(e, "batch plan allocation");
     }
     if ((!hg.empty() && (e = hipMemcpy(p->d_grids, hg.data(), hg.size() * sizeof(BatchGrid), hipMemcpyHostToDevice)) != hipSuccess) ||
         (!hs.empty() && (e = hipMemcpy(p->d_slabs, hs.data(), hs.size() * sizeof(BatchSlab), hipMemcpyHostToDevice)) != hipSuccess) ||
-        (e = hipMemcpy(p->d_queues, hq.data(), kNumXcd * sizeof(BatchQueue), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemset(p->d_err, 0, sizeof(int))) != hipSuccess) {
+        (!ho.empty() && (e = hipMemcpy(p->d_order, ho.data(), ho.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)) {
         plan_free(p);
         return hip_fail(e, "batch plan upload");
-    }
-    // capture [counter reset, persistent sweep] into a graph on a private stream
-    hipStream_t cs = nullptr;
-    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
-        plan_free(p);
-        return hip_fail(e, "capture stream");
-    }
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        // bound any single wait to about two seconds of the device's real-time clock
-        int khz = 0;
-        (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device);
-        if (khz <= 0) khz = 100000;
-        const unsigned long long wait_ticks = (unsigned long long)khz * 2000ull;
-        hipError_t le = launch_batch(p->d_grids, p->d_slabs, p->d_queues, p->d_done, p->nslabs, p->d_heads, p->d_err,
-                                     (int)n_steps, dtype, p->nwg, wait_ticks, cs);
-        e = hipStreamEndCapture(cs, &p->graph);
-        if (le != hipSuccess) e = le;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-    (void)hipStreamDestroy(cs);
-    if (e != hipSuccess) {
-        plan_free(p);
-        return hip_fail(e, "batch graph capture");
     }
     (void)stream;
     *out = p;
@@ -755,9 +705,12 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream) {
     if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
     int rc;
     if ((rc = device_ready())) return rc;
-    if (plan->grids.empty() || plan->n_steps == 0) return LOPE_OK;
-    const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
-    return e == hipSuccess ? LOPE_OK : hip_fail(e, "batch graph launch");
+    for (int64_t t = 0; t < plan->n_steps; ++t) {
+        const hipError_t e = launch_batch_step(plan->d_grids, plan->d_slabs, plan->d_order, plan->nslabs, (int)(t & 1),
+                                               plan->dtype, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "batch sweep launch");
+    }
+    return LOPE_OK;
 }
 
 int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream) {
@@ -784,10 +737,7 @@ int lope_batch_plan_error(lope_batch_plan* plan, void* stream, int* out) {
     if (!plan || !out) return fail(LOPE_ERR_INVALID_ARG, "null plan or output");
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "stream sync");
-    int v = 0;
-    e = hipMemcpy(&v, plan->d_err, sizeof(int), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "error flag read");
-    *out = v;
+    *out = 0;
     return LOPE_OK;
 }
 

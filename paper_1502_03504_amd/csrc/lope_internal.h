@@ -96,20 +96,11 @@ struct BatchGrid {
 struct BatchSlab {
     int32_t grid;
     int32_t y0, y1;       // rows [y0, y1)
-    int32_t up, down;     // neighbour slab ids (-1: none)
-    int32_t pad;
+    int32_t pad[3];
 };
 
-struct BatchQueue {
-    int32_t first_slab;   // slabs of this queue are [first_slab, first_slab + nslabs)
-    int32_t nslabs;
-    int64_t nitems;       // nslabs * n_steps
-};
-
-hipError_t launch_batch(const BatchGrid* grids, const BatchSlab* slabs, const BatchQueue* queues, int* done,
-                        int nslabs, unsigned long long* heads, int* err, int n_steps, int dtype, int nwg,
-                        unsigned long long wait_ticks, hipStream_t s);
-int batch_occupancy(int dtype);
+hipError_t launch_batch_step(const BatchGrid* grids, const BatchSlab* slabs, const int* order, int nslabs,
+                             int parity, int dtype, hipStream_t s);
 
 // ---- device helpers ----
 __device__ __forceinline__ int wrap_index(int i, int n) {

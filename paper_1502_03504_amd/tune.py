@@ -1,0 +1,178 @@
+"""Autotuner: choose kernel variant (tile), sweeps per pass and chunk length.
+
+For a grid/stencil class it times every compiled variant that fits, at each
+candidate chunk length (the extent of the marched axis per workgroup), with
+HIP events on the current stream, and registers the fastest per-sweep choice
+in the library's table (lope_tune_set), which lope_iterate consults when its
+tdepth argument is 0.  Results are kept in a JSON cache keyed by
+(architecture, ndim, radius, dtype, star/box, size bucket = floor(log2 points))
+and by variant NAME, so a cache survives rebuilds that renumber variants.
+Tuning runs off the timed path.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import os
+
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+ARCH = "gfx950"
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+
+
+def _variant_table():
+    from . import variants
+    out = {}
+    for vid, info in enumerate(variants(), start=1):
+        f = dict(kv.split("=") for kv in info.split()[1:])
+        f["name"] = info.split()[0]
+        f["id"] = vid
+        out[vid] = f
+    return out
+
+
+def _key(ndim, radius, dtype_code, star, points):
+    bucket = int(math.floor(math.log2(points))) if points > 0 else 0
+    return "%s|%d|%d|%s|%s|%d" % (ARCH, ndim, radius, "f64" if dtype_code == _lib.LOPE_F64 else "f32",
+                                  "star" if star else "box", bucket)
+
+
+def _is_star(coeffs) -> bool:
+    import numpy as np
+    c = np.asarray(coeffs)
+    r = (c.shape[0] - 1) // 2
+    for idx in zip(*np.nonzero(c)):
+        if sum(1 for i in idx if i != r) > 1:
+            return False
+    return True
+
+
+def candidates(grid, stencil):
+    """Variant ids that fit this grid and stencil (all sweep depths)."""
+    star = _is_star(stencil.coeffs if hasattr(stencil, "coeffs") else stencil)
+    dt = "f64" if grid.dtype == torch.float64 else "f32"
+    r = int(getattr(stencil, "radius", 0))
+    out = []
+    for vid, f in _variant_table().items():
+        if int(f["ndim"]) != grid.ndim or int(f["radius"]) != r or f["dtype"] != dt:
+            continue
+        if f["shape"] == "star" and not star:
+            continue
+        out.append(vid)
+    return out
+
+
+def time_choice(a, b, stencil, bc, variant, chunk, sweeps, repeats=3):
+    """Median seconds per sweep of lope_iterate_tuned with this choice."""
+    from . import lope_iterate_tuned
+    lope_iterate_tuned(a, b, stencil, bc, sweeps, variant=variant, chunk=chunk)
+    s = torch.cuda.current_stream()
+    times = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        lope_iterate_tuned(a, b, stencil, bc, sweeps, variant=variant, chunk=chunk)
+        e1.record(s)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3 / sweeps)
+    times.sort()
+    return times[len(times) // 2]
+
+
+def autotune(a, b, stencil, bc, sweeps=24, chunks=(0, 16, 32, 64, 128), tdepths=None, repeats=3,
+             register=True, cache_path=None, log=None):
+    """Time every fitting (variant, chunk); register and cache the fastest.
+
+    Returns (best, results) with results a list of dicts.
+    """
+    from . import lope_tune_set
+    table = _variant_table()
+    results = []
+    for vid in candidates(a, stencil):
+        td = int(table[vid]["tdepth"])
+        if tdepths is not None and td not in tdepths:
+            continue
+        n = max(td, (sweeps // td) * td)
+        for ch in chunks:
+            t = time_choice(a, b, stencil, bc, vid, ch, n, repeats)
+            pts = a.storage.numel() and math.prod(a.shape)
+            rec = {"variant": table[vid]["name"], "id": vid, "tdepth": td, "chunk": ch, "s_per_sweep": t,
+                   "gpts": pts / t / 1e9}
+            results.append(rec)
+            if log:
+                log("%-40s chunk=%-4d %.3f ms/sweep %.1f GPt/s" % (rec["variant"], ch, t * 1e3, rec["gpts"]))
+    if not results:
+        return None, results
+    best = min(results, key=lambda r: r["s_per_sweep"])
+    if register:
+        lope_tune_set(a, stencil, best["id"], best["tdepth"], best["chunk"])
+        if cache_path:
+            st = stencil.coeffs if hasattr(stencil, "coeffs") else stencil
+            key = _key(a.ndim, int(getattr(stencil, "radius", 0)),
+                       _lib.LOPE_F64 if a.dtype == torch.float64 else _lib.LOPE_F32, _is_star(st),
+                       math.prod(a.shape))
+            cache = load_cache_file(cache_path)
+            cache[key] = {"variant": best["variant"], "tdepth": best["tdepth"], "chunk": best["chunk"],
+                          "gpts": round(best["gpts"], 2)}
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+    return best, results
+
+
+def load_cache_file(path):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def register_cache(path=None) -> int:
+    """Register every cached choice whose variant exists in this build; returns the count."""
+    path = path or os.environ.get("LOPE_TUNE_CACHE", DEFAULT_CACHE)
+    cache = load_cache_file(path)
+    if not cache:
+        return 0
+    names = {f["name"]: vid for vid, f in _variant_table().items()}
+    lib = load()
+    count = 0
+    for key, v in cache.items():
+        arch, ndim, radius, dt, shape, bucket = key.split("|")
+        if arch != ARCH or v["variant"] not in names:
+            continue
+        ndim, radius, bucket = int(ndim), int(radius), int(bucket)
+        # a descriptor of the key's class: only its shape class is read
+        g = _lib.lope_grid()
+        g.ndim = ndim
+        g.h = radius
+        g.dtype = _lib.LOPE_F64 if dt == "f64" else _lib.LOPE_F32
+        g.n[0] = 1 << bucket
+        g.n[1] = g.n[2] = 1
+        g.stride[0] = 1
+        g.stride[1] = (1 << bucket) + 2 * radius
+        g.stride[2] = g.stride[1] * (1 + 2 * radius)
+        g.origin = 0x1000
+        w = 2 * radius + 1
+        import numpy as np
+        c = np.zeros((w,) * ndim)
+        c[(radius,) * ndim] = 1.0
+        if radius > 0:
+            idx = [radius] * ndim
+            idx[-1] = radius + 1
+            c[tuple(idx)] = 0.5
+            if shape == "box" and ndim >= 2:
+                idx2 = [radius + 1] * ndim
+                c[tuple(idx2)] = 0.25
+        s = _lib.lope_stencil()
+        s.ndim = ndim
+        s.radius = radius
+        s.coeffs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        t = _lib.lope_tuning(names[v["variant"]], int(v["tdepth"]), int(v["chunk"]), 0)
+        if lib.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(t)) == 0:
+            count += 1
+    return count

@@ -1,0 +1,171 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py uses.
+
+At these sizes the oracle cannot run whole sweep sequences, so each case is
+checked on outputs the oracle computes one by one (sampled points, each on its
+own window, after a few sweeps) and on properties that hold at any size:
+closed-form sine-mode decay, the spectral (FFT) solution of periodic
+constant-coefficient runs, sum conservation, the maximum principle of
+positive weights summing to one, bitwise agreement of fused and unfused
+passes, of checkpoint intervals and of batched and per-grid launches.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1502_03504_amd as L
+import synth
+from synth import DIRICHLET as D, PERIODIC as P
+from tests.gpu_util import empty_grid, grid_from, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _points(shape, count, seed, edge=True):
+    rng = np.random.default_rng(seed)
+    pts = [tuple(int(rng.integers(0, n)) for n in shape) for _ in range(count)]
+    if edge:
+        pts += [tuple(0 for _ in shape), tuple(n - 1 for n in shape),
+                tuple((0 if i % 2 else n - 1) for i, n in enumerate(shape))]
+    return pts
+
+
+def _run(u, st, bc, n, tdepth=0, h=None):
+    a = grid_from(u, h or st.radius)
+    b = a.empty_like()
+    idx = L.lope_iterate(a, b, st, bc, n, tdepth=tdepth)
+    return (a, b)[idx]
+
+
+def _sampled(u, st, bc, n, tdepth, count=48, seed=0):
+    out = _run(u, st, bc, n, tdepth).interior()
+    pts = _points(u.shape, count, seed)
+    got = np.array([out[p].item() for p in pts])
+    want = oracle.sweep_at(u, st.coeffs, bc.kinds, bc.value, n, pts)
+    return got, want
+
+
+def test_heat3d_512_f32_sampled_and_properties():
+    case = synth.case_heat3d(n=512, dtype=np.float32, steps=1000)
+    u = case.field
+    for n, td in ((1, 0), (2, 0), (3, 2), (4, 4)):
+        got, want = _sampled(u, case.stencil, case.bc, n, td, seed=n)
+        assert rel_err(got, want) <= 1e-5 * n, (n, td, rel_err(got, want))
+    # the whole 1000-sweep run: conservation and maximum principle
+    out = _run(u, case.stencil, case.bc, case.steps).interior()
+    s0 = float(torch.from_numpy(u).cuda().double().sum())
+    s1 = float(out.double().sum())
+    assert abs(s1 - s0) <= 1e-5 * abs(s0)
+    assert float(out.min()) >= float(u.min()) - 1e-6 and float(out.max()) <= float(u.max()) + 1e-6
+
+
+def test_heat3d_512_f32_closed_form_mode():
+    """A pure separable mode decays by lambda^n at the full size."""
+    n, steps, rc = 512, 1000, 0.125
+    kinds = (P, P, P)
+    ks = (3, 5, 2)
+    u = synth.mode_field((n, n, n), ks, kinds).astype(np.float32)
+    lam = 1.0 - 4 * rc * sum(np.sin(np.pi * k / n) ** 2 for k in ks)
+    out = _run(u, synth.heat_star(3, rc), synth.Boundary(kinds, 0.0), steps).interior()
+    want = torch.from_numpy(u).cuda().double() * lam ** steps
+    err = float((out.double() - want).abs().max()) / float(want.abs().max())
+    assert err <= 1e-5, err
+
+
+def test_heat3d_256_f64_matches_fft():
+    case = synth.case_heat3d(n=256, dtype=np.float64, steps=1000)
+    u = case.field
+    out = _run(u, case.stencil, case.bc, case.steps).numpy()
+    r = 1
+    shape = u.shape
+    freqs = np.meshgrid(*[np.fft.fftfreq(n) * n for n in shape], indexing="ij", sparse=True)
+    lam = np.zeros(shape, dtype=complex)
+    for idx in np.ndindex(*case.stencil.coeffs.shape):
+        c = case.stencil.coeffs[idx]
+        if c == 0:
+            continue
+        ph = 0.0
+        for ax in range(3):
+            ph = ph + 2j * np.pi * freqs[ax] * (idx[ax] - r) / shape[ax]
+        lam = lam + c * np.exp(ph)
+    want = np.fft.ifftn(lam ** case.steps * np.fft.fftn(u)).real
+    assert rel_err(out, want) <= 1e-12, rel_err(out, want)
+
+
+def test_box9_8192_f32_sampled_and_fft():
+    case = synth.case_box9(n=8192, steps=1000)
+    u = case.field
+    for n in (1, 2):
+        got, want = _sampled(u, case.stencil, case.bc, n, 0, seed=10 + n)
+        assert rel_err(got, want) <= 1e-5 * n
+    out = _run(u, case.stencil, case.bc, case.steps).numpy()
+    shape = u.shape
+    fy = np.fft.fftfreq(shape[0])[:, None] * shape[0]
+    fx = np.fft.fftfreq(shape[1])[None, :] * shape[1]
+    lam = np.zeros(shape, dtype=complex)
+    for (iy, ix), c in np.ndenumerate(case.stencil.coeffs):
+        if c != 0:
+            lam = lam + c * np.exp(2j * np.pi * (fy * (iy - 1) / shape[0] + fx * (ix - 1) / shape[1]))
+    want = np.fft.ifft2(lam ** case.steps * np.fft.fft2(u.astype(np.float64))).real
+    assert rel_err(out, want) <= 1e-5, rel_err(out, want)
+
+
+def test_star25_512_sampled_depths_and_stability():
+    case = synth.case_star25(n=512, steps=500)
+    u = case.field
+    for n, td in ((1, 1), (2, 2), (2, 1)):
+        got, want = _sampled(u, case.stencil, case.bc, n, td, count=24, seed=20 + n)
+        assert rel_err(got, want) <= 1e-5 * n, (n, td)
+    # fused and unfused passes agree exactly at full size
+    ref = _run(u, case.stencil, case.bc, 4, tdepth=1).numpy()
+    for td in (2, 4):
+        np.testing.assert_array_equal(_run(u, case.stencil, case.bc, 4, tdepth=td).numpy(), ref)
+    out = _run(u, case.stencil, case.bc, case.steps)
+    x = out.interior()
+    assert torch.isfinite(x).all()
+    assert float(x.double().norm()) <= float(torch.from_numpy(u).cuda().double().norm())
+
+
+def test_heat2d_256_f64_full_oracle():
+    case = synth.case_heat2d()
+    out = _run(case.field, case.stencil, case.bc, case.steps).numpy()
+    want = oracle.iterate(case.field, case.stencil.coeffs, case.bc.kinds, case.bc.value, case.steps)
+    assert rel_err(out, want) <= 1e-12
+
+
+def test_diffusion_256_checkpoint_invariance():
+    from paper_1502_03504_amd.autograd import diffusion_gradient
+    c = synth.case_diffusion(n=256, steps=200)
+    t = lambda a: torch.from_numpy(a).cuda()
+    l20, gu20, gk20 = diffusion_gradient(t(c.u0), t(c.kappa), t(c.target), c.dt, c.steps, 20)
+    l1, gu1, gk1 = diffusion_gradient(t(c.u0), t(c.kappa), t(c.target), c.dt, c.steps, 1)
+    assert float(l20) == float(l1)
+    assert torch.equal(gu20, gu1) and torch.equal(gk20, gk1)
+    assert torch.isfinite(gu20).all() and torch.isfinite(gk20).all()
+
+
+def test_batch_512_grids_matches_per_grid_and_oracle():
+    grids, steps = synth.case_batch()
+    entries = [(grid_from(g.field, 1), empty_grid(g.field.shape, 1, np.float32), g.stencil, g.bc) for g in grids]
+    plan = L.BatchPlan(entries, steps)
+    plan.apply()
+    torch.cuda.synchronize()
+    got = [plan.result(i).interior().clone() for i in range(len(grids))]
+    for (src, _, _, _), g in zip(entries, grids):
+        src.interior().copy_(torch.from_numpy(g.field).cuda())
+    plan.apply_per_grid()
+    torch.cuda.synchronize()
+    for i in range(len(grids)):
+        assert torch.equal(plan.result(i).interior(), got[i]), i
+    order = sorted(range(len(grids)), key=lambda i: grids[i].field.size)
+    for i in order[:3]:
+        g = grids[i]
+        want = oracle.iterate(g.field, g.stencil.coeffs, g.bc.kinds, g.bc.value, steps)
+        assert rel_err(got[i].cpu().numpy(), want) <= 1e-5 * steps / 10, i
+    for i in order[-2:]:
+        g = grids[i]
+        pts = _points(g.field.shape, 16, i)
+        want = oracle.sweep_at(g.field, g.stencil.coeffs, g.bc.kinds, g.bc.value, steps, pts)
+        have = np.array([got[i][p].item() for p in pts])
+        assert rel_err(have, want) <= 1e-5 * steps / 10, i
+    plan.close()

@@ -206,6 +206,9 @@ def _batch_entries(rng, count, dtype, lo=3, hi=300):
     return entries, fields
 
 
+@pytest.mark.skip(reason="the persistent work-queue batch kernel hung on the GPU twice (second time after "
+                         "a fix of its polling); its cause is not shown, so that path is switched off and "
+                         "this case stays off the GPU; the step-wise batch path is tested below")
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_batch_matches_per_grid_and_oracle(dtype):
     rng = np.random.default_rng([synth.CFG_TEST, 400])
@@ -228,6 +231,29 @@ def test_batch_matches_per_grid_and_oracle(dtype):
     # a second launch of the same graph continues from the current state
     plan.apply()
     assert plan.error() == 0
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
+    """One launch per sweep over every slab of every grid (no waits between
+    workgroups) against the oracle and against one launch per grid per sweep."""
+    rng = np.random.default_rng([synth.CFG_TEST, 401])
+    n = 9
+    entries, fields = _batch_entries(rng, 24, dtype)
+    plan = L.BatchPlan(entries, n)
+    plan.apply()
+    torch.cuda.synchronize()
+    got = [plan.result(i).numpy() for i in range(len(entries))]
+    for i, (e, u) in enumerate(zip(entries, fields)):
+        want = oracle.iterate(u, e[2].coeffs, e[3][0], e[3][1], n)
+        assert rel_err(got[i], want) <= tol(dtype) * n, i
+    for (src, dst, _, _), u in zip(entries, fields):
+        src.interior().copy_(torch.from_numpy(u).cuda())
+    plan.apply_per_grid()
+    torch.cuda.synchronize()
+    for i in range(len(entries)):
+        np.testing.assert_array_equal(plan.result(i).numpy(), got[i])
     plan.close()
 
 
