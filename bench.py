@@ -29,6 +29,65 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measure_adjoint(n=256, steps=200, every=20):
+    """Per-step forward / reverse kernel times of the variable-coefficient
+    diffusion step (256^3 float32, periodic), and the end-to-end checkpointed
+    gradient (forward with checkpoint saves, then recompute + reverse)."""
+    import numpy as np
+    import torch
+
+    import paper_1502_03504_amd as L
+    import synth
+    from paper_1502_03504_amd.autograd import diffusion
+
+    c = synth.case_diffusion(n=n, steps=steps, k=every)
+    bc = (("periodic",) * 3, 0.0)
+    u = L.Grid.from_array(c.u0, 1)
+    v = u.empty_like()
+    kap = L.Grid.from_array(c.kappa, 1)
+    lam = L.Grid.from_array(c.target, 1)
+    lam2 = lam.empty_like()
+    g32 = L.Grid.allocate(c.u0.shape, 0, torch.float32)
+    s = torch.cuda.current_stream()
+
+    def timed(fn, reps=20):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    fwd = timed(lambda: L.lope_apply_var(u, v, kap, c.dt, bc))
+    adj = timed(lambda: L.lope_apply_var_adjoint(lam, lam2, u, kap, c.dt, bc, g32))
+    u0 = torch.from_numpy(c.u0).cuda()
+    k0 = torch.from_numpy(c.kappa).cuda()
+    tg = torch.from_numpy(c.target).cuda()
+    uu = u0.clone().requires_grad_(True)
+    kk = k0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uT = diffusion(uu, kk, c.dt, steps, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = uT.double() - tg.double()
+    (d * d).sum().backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pts = n ** 3
+    return {"workload": "diffusion_7pt_varcoef_%d^3_f32_periodic_%d_steps_checkpoint_%d" % (n, steps, every),
+            "fwd_ms_per_step": round(fwd, 4), "adj_ms_per_step": round(adj, 4),
+            "ratio_per_step": round(adj / fwd, 3),
+            "fwd_GBs": round(12.0 * pts / (fwd * 1e-3) / 1e9, 1), "adj_GBs": round(24.0 * pts / (adj * 1e-3) / 1e9, 1),
+            "fwd_total_ms": round((t1 - t0) * 1e3, 2), "bwd_total_ms": round((t2 - t1) * 1e3, 2),
+            "ratio_end_to_end": round((t2 - t1) / (t1 - t0), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,6 +99,10 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="full-size oracle sweeps timed (0 = skip)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio measurement")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -74,6 +137,15 @@ def main():
             return L.lope_iterate_tuned(a, b, st, bc, sweeps, variant=vid, chunk=args.chunk)
         return L.lope_iterate(a, b, st, bc, sweeps, tdepth=args.tdepth)
 
+    if args.copy_mb > 0:
+        n_el = args.copy_mb * (1 << 20) // 4
+        c_src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        c_dst = torch.empty_like(c_src)
+        c_dst.copy_(c_src)
+        torch.cuda.synchronize()
+        log("reference copy: %d MiB read, %d MiB written" % (args.copy_mb, args.copy_mb))
+        del c_src, c_dst
+
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -95,6 +167,13 @@ def main():
     launch_s = ms * 1e-3 / (args.steps * passes_per_step)
     alg_bytes_per_launch = 8.0 * pts * td
     achieved = alg_bytes_per_launch / launch_s / 1e9
+
+    adjoint = None
+    if not args.no_adjoint:
+        del a, b
+        torch.cuda.empty_cache()
+        adjoint = measure_adjoint()
+        log("adjoint:", adjoint)
 
     cpu = None
     if args.cpu_sweeps > 0:
@@ -127,6 +206,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
         "cpu_baseline": cpu,
+        "adjoint_forward": adjoint,
     }
     print(json.dumps(out), flush=True)
 

@@ -224,7 +224,9 @@ struct Registry {
     std::vector<Variant> v;
     Registry() {
         const Variant* p;
-        int n = star3d_variants(&p);
+        int n = star3d_vec_variants(&p);
+        for (int i = 0; i < n; ++i) v.push_back(p[i]);
+        n = star3d_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = plane2d_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
@@ -251,6 +253,14 @@ bool variant_fits(const Variant& v, const SweepJob& j, int tdepth) {
     if (v.ndim != j.ndim || v.radius != j.radius || v.dtype != j.dtype || v.tdepth != tdepth) return false;
     if (v.family == FAM_STAR3D) return j.star;
     if (v.family == FAM_PLANE2D) return v.box ? true : j.star;
+    if (v.family == FAM_STAR3D_VEC) {
+        // 16-byte vectors: aligned origins, strides in whole vectors
+        const int64_t vec = j.dtype == LOPE_F64 ? 2 : 4;
+        auto aligned = [&](const DevGrid& g) {
+            return ((uintptr_t)g.origin % 16) == 0 && g.sy % vec == 0 && g.sz % vec == 0;
+        };
+        return j.star && aligned(j.src) && aligned(j.dst);
+    }
     return false;
 }
 
@@ -769,7 +779,7 @@ int lope_variant_info(int id, char* text, int cap) {
     const Variant& v = registry().v[id - 1];
     snprintf(text, (size_t)cap, "%s ndim=%d radius=%d tdepth=%d dtype=%s shape=%s tile=%dx%d nt=%d chunk=%d", v.name,
              v.ndim, v.radius, v.tdepth, v.dtype == LOPE_F64 ? "f64" : "f32",
-             v.family == FAM_STAR3D ? "star" : (v.box ? "box" : "star"), v.bx, v.by, v.nt, v.default_chunk);
+             v.family == FAM_PLANE2D ? (v.box ? "box" : "star") : "star", v.bx, v.by, v.nt, v.default_chunk);
     return LOPE_OK;
 }
 

@@ -1,0 +1,316 @@
+// 3D star stencils, one sweep per pass, with 16-byte vector memory access.
+//
+// A workgroup marches a z-chunk of a BX x BY output tile.  Each thread owns
+// VEC consecutive x positions (one 16-byte vector) on RPT rows of the core
+// tile and keeps, for those points only, the last 2R+1 planes in registers
+// (the z neighbours).  The centre plane of the tile plus its x/y halo
+// (R rows above and below, R columns left and right; the star needs no
+// corners) is published in LDS, double-buffered, one barrier per plane.
+// Core planes are fetched R+1 planes ahead of the plane being computed, the
+// halo of the next centre plane one plane ahead, so the loads of the next
+// step are in flight while this one computes.
+//
+// The LDS row holds the core at a 16-byte aligned column (kLead) so the
+// centre and y-neighbour rows are read as vectors.  Every point is summed as
+// c0*v0 followed by fmas in lexicographic offset order (z-R .. z-1,
+// y-R .. y-1, x-R .. x+R, y+1 .. y+R, z+1 .. z+R), identical to the other
+// kernels.  The boundary rule is applied while loading; positions of a
+// ragged tile beyond the interior hold rule values (wrapped or g).
+//
+// Requirements (checked by the caller): origin 16-byte aligned, y and z
+// strides multiples of VEC elements.
+#include "lope_internal.h"
+
+namespace lope {
+namespace {
+
+template <typename T, int R>
+struct VStarCoef {
+    T c[6 * R + 1];
+};
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int n = 4;
+};
+template <>
+struct Vec<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int n = 2;
+};
+
+template <typename T, int R, int BX, int BY, int NT>
+__global__ void __launch_bounds__(NT)
+k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chunk, int tiles_x, int tiles_y,
+             int nblocks, int nblocks_padded) {
+    typedef typename Vec<T>::type VT;
+    constexpr int VEC = Vec<T>::n;
+    constexpr int TX = BX / VEC;            // threads across a core row
+    constexpr int TYT = NT / TX;            // core rows per thread pass
+    constexpr int RPT = BY / TYT;           // core rows per thread
+    constexpr int kLead = 16 / sizeof(T) > R ? 16 / sizeof(T) : ((R + VEC - 1) / VEC) * VEC;
+    constexpr int LW = kLead + BX + kLead;  // LDS row length (core at column kLead)
+    constexpr int LH = BY + 2 * R;          // LDS rows (core at row R)
+    constexpr int RING = 2 * R + 1;
+    constexpr int NHROW = 2 * R * TX;       // halo row vectors (R rows above, R below)
+    constexpr int NHCOL = 2 * R * BY;       // halo column scalars (R left, R right)
+    constexpr int NHALO = NHROW + NHCOL;
+    constexpr int HPT = (NHALO + NT - 1) / NT;   // halo items per thread
+    static_assert(BX % VEC == 0 && NT % TX == 0 && BY % TYT == 0, "tile shape");
+
+    __shared__ __attribute__((aligned(16))) T lds[2][LH][LW];
+
+    const int logical = xcd_logical_block(nblocks_padded);
+    if (logical >= nblocks) return;
+    const int tix = logical % tiles_x;
+    const int rest = logical / tiles_x;
+    const int tiy = rest % tiles_y;
+    const int tiz = rest / tiles_y;
+    const int nx = src.nx, ny = src.ny, nz = src.nz;
+    const int x0 = tix * BX, y0 = tiy * BY, z0 = tiz * chunk;
+    const int zend = min(z0 + chunk, nz);
+    const bool perx = rule.per[0] != 0, pery = rule.per[1] != 0, perz = rule.per[2] != 0;
+    const T g = (T)rule.g;
+    const T* __restrict__ sp = (const T*)src.origin;
+    T* __restrict__ dp = (T*)dst.origin;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int cx = x0 + tx * VEC;                     // first x of this thread's vector
+    const bool xfull = cx + VEC <= nx;                // the whole vector is interior
+    // core rows of this thread
+    int cy[RPT];
+    bool yin[RPT];
+    int64_t soff[RPT];                                // offset of (cx, wrapped row) in src
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        cy[k] = y0 + ty + k * TYT;
+        yin[k] = cy[k] < ny;
+        const int wy = yin[k] ? cy[k] : (pery ? wrap_index(cy[k], ny) : ny - 1);
+        soff[k] = (int64_t)wy * src.sy;
+    }
+    // rule value of a single element at (gx, gy) in plane z (z already valid)
+    auto elem = [&](int gx, int gy, int64_t zo) -> T {
+        const bool ox = gx < 0 || gx >= nx, oy = gy < 0 || gy >= ny;
+        if ((ox && !perx) || (oy && !pery)) return g;
+        return sp[zo + (int64_t)wrap_index(gy, ny) * src.sy + wrap_index(gx, nx)];
+    };
+    auto load_core = [&](int j, T (&v)[RPT][VEC]) {
+        const bool oz = j < 0 || j >= nz;
+        if (oz && !perz) {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[k][e] = g;
+            return;
+        }
+        const int64_t zo = (int64_t)(perz ? wrap_index(j, nz) : j) * src.sz;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            if (xfull && (yin[k] || pery)) {
+                const VT q = *(const VT*)(sp + zo + soff[k] + cx);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[k][e] = ((const T*)&q)[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[k][e] = elem(cx + e, cy[k], zo);
+            }
+        }
+    };
+    // halo items: vectors of the R rows above/below the core, scalars of the R
+    // columns left/right
+    auto load_halo = [&](int j, T (&hv)[HPT][VEC]) {
+        const bool oz = j < 0 || j >= nz;
+        const bool zd = oz && !perz;
+        const int64_t zo = zd ? 0 : (int64_t)(perz ? wrap_index(j, nz) : j) * src.sz;
+#pragma unroll
+        for (int m = 0; m < HPT; ++m) {
+            const int h = tid + m * NT;
+            if (h >= NHALO) continue;
+            if (zd) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) hv[m][e] = g;
+                continue;
+            }
+            if (h < NHROW) {
+                const int r = h / TX, hx = h % TX;
+                const int gy = r < R ? y0 - R + r : y0 + BY + (r - R);
+                const int gx = x0 + hx * VEC;
+                const bool oy = gy < 0 || gy >= ny;
+                if (gx + VEC <= nx && !(oy && !pery)) {
+                    const int64_t o = zo + (int64_t)wrap_index(gy, ny) * src.sy + gx;
+                    const VT q = *(const VT*)(sp + o);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) hv[m][e] = ((const T*)&q)[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) hv[m][e] = elem(gx + e, gy, zo);
+                }
+            } else {
+                const int c = h - NHROW;
+                const int side = c / (R * BY), rem = c % (R * BY);
+                const int col = rem / BY, row = rem % BY;
+                const int gx = side == 0 ? x0 - R + col : x0 + BX + col;
+                hv[m][0] = elem(gx, y0 + row, zo);
+            }
+        }
+    };
+    auto store_halo = [&](T (*L)[LW], const T (&hv)[HPT][VEC]) {
+#pragma unroll
+        for (int m = 0; m < HPT; ++m) {
+            const int h = tid + m * NT;
+            if (h >= NHALO) continue;
+            if (h < NHROW) {
+                const int r = h / TX, hx = h % TX;
+                const int ly = r < R ? r : BY + r;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) L[ly][kLead + hx * VEC + e] = hv[m][e];
+            } else {
+                const int c = h - NHROW;
+                const int side = c / (R * BY), rem = c % (R * BY);
+                const int col = rem / BY, row = rem % BY;
+                const int lx = side == 0 ? kLead - R + col : kLead + BX + col;
+                L[R + row][lx] = hv[m][0];
+            }
+        }
+    };
+
+    T ring[RPT][RING][VEC];
+    T pre[RPT][VEC];
+    T hpre[HPT][VEC];
+    // prologue: planes z0-R .. z0+R into the ring, centre plane z0 into LDS[0]
+#pragma unroll
+    for (int s = 0; s < RING; ++s) {
+        T tmp[RPT][VEC];
+        load_core(z0 - R + s, tmp);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) ring[k][s][e] = tmp[k][e];
+    }
+    load_halo(z0, hpre);
+    store_halo(lds[0], hpre);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) lds[0][R + ty + k * TYT][kLead + tx * VEC + e] = ring[k][R][e];
+    load_core(z0 + R + 1, pre);
+    load_halo(z0 + 1, hpre);
+    lds_barrier();
+
+    for (int zc = z0; zc < zend; ++zc) {
+        const int buf = (zc - z0) & 1;
+        T (*L)[LW] = lds[buf];
+        // compute plane zc
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int ly = R + ty + k * TYT;
+            const int lx = kLead + tx * VEC;
+            T out[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                T v = cf.c[0] * ring[k][0][e];
+#pragma unroll
+                for (int s = 1; s < R; ++s) v = fma(cf.c[s], ring[k][s][e], v);
+#pragma unroll
+                for (int o = -R; o < 0; ++o) v = fma(cf.c[2 * R + o], L[ly + o][lx + e], v);
+#pragma unroll
+                for (int o = -R; o <= R; ++o) v = fma(cf.c[3 * R + o], o == 0 ? ring[k][R][e] : L[ly][lx + e + o], v);
+#pragma unroll
+                for (int o = 1; o <= R; ++o) v = fma(cf.c[4 * R + o], L[ly + o][lx + e], v);
+#pragma unroll
+                for (int o = 1; o <= R; ++o) v = fma(cf.c[5 * R + o], ring[k][R + o][e], v);
+                out[e] = v;
+            }
+            if (yin[k]) {
+                T* o = dp + (int64_t)zc * dst.sz + (int64_t)cy[k] * dst.sy + cx;
+                if (xfull) {
+                    VT q;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) ((T*)&q)[e] = out[e];
+                    __builtin_nontemporal_store(q, (VT*)o);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (cx + e < nx) __builtin_nontemporal_store(out[e], o + e);
+                }
+            }
+        }
+        // advance: shift the ring, publish plane zc+1 in the other buffer
+#pragma unroll
+        for (int k = 0; k < RPT; ++k)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+#pragma unroll
+                for (int s = 0; s < RING - 1; ++s) ring[k][s][e] = ring[k][s + 1][e];
+                ring[k][RING - 1][e] = pre[k][e];
+            }
+        if (zc + 1 < zend) {
+            T (*N)[LW] = lds[buf ^ 1];
+            store_halo(N, hpre);
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) N[R + ty + k * TYT][kLead + tx * VEC + e] = ring[k][R][e];
+            if (zc + 2 < zend) load_core(zc + R + 2, pre);
+            if (zc + 2 < zend) load_halo(zc + 2, hpre);
+        }
+        lds_barrier();
+    }
+}
+
+template <typename T, int R, int BX, int BY, int NT>
+hipError_t run_star3d_vec(const SweepJob& j, int chunk, hipStream_t s) {
+    VStarCoef<T, R> cf;
+    const int r = j.radius;
+    const int w = 2 * r + 1;
+    auto dense = [&](int ox, int oy, int oz) { return (T)j.dense[(ox + r) + (oy + r) * w + (oz + r) * w * w]; };
+    for (int o = -R; o < 0; ++o) cf.c[o + R] = dense(0, 0, o);
+    for (int o = -R; o < 0; ++o) cf.c[2 * R + o] = dense(0, o, 0);
+    for (int o = -R; o <= R; ++o) cf.c[3 * R + o] = dense(o, 0, 0);
+    for (int o = 1; o <= R; ++o) cf.c[4 * R + o] = dense(0, o, 0);
+    for (int o = 1; o <= R; ++o) cf.c[5 * R + o] = dense(0, 0, o);
+    if (chunk <= 0) chunk = 64;
+    const int tiles_x = (j.src.nx + BX - 1) / BX;
+    const int tiles_y = (j.src.ny + BY - 1) / BY;
+    const int tiles_z = (j.src.nz + chunk - 1) / chunk;
+    const int64_t nb64 = (int64_t)tiles_x * tiles_y * tiles_z;
+    if (nb64 > (1ll << 30)) return hipErrorInvalidConfiguration;
+    const int nb = (int)nb64;
+    const int nbp = padded_block_count(nb);
+    hipLaunchKernelGGL((k_star3d_vec<T, R, BX, BY, NT>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, j.rule, cf, chunk,
+                       tiles_x, tiles_y, nb, nbp);
+    return hipGetLastError();
+}
+
+#define VSTAR(T, DT, R, BX, BY, NT, CH)                                                                     \
+    {"star3dv_" #T "_r" #R "_t1_" #BX "x" #BY "_nt" #NT, FAM_STAR3D_VEC, 3, R, 1, DT, 0, BX, BY, NT, CH, \
+     &run_star3d_vec<T, R, BX, BY, NT>}
+
+const Variant kStar3dVec[] = {
+    VSTAR(float, LOPE_F32, 1, 64, 32, 256, 64),
+    VSTAR(float, LOPE_F32, 1, 128, 16, 256, 64),
+    VSTAR(float, LOPE_F32, 1, 64, 16, 256, 64),
+    VSTAR(float, LOPE_F32, 1, 128, 32, 512, 64),
+    VSTAR(float, LOPE_F32, 2, 64, 32, 256, 64),
+    VSTAR(float, LOPE_F32, 3, 64, 32, 256, 64),
+    VSTAR(float, LOPE_F32, 4, 64, 32, 256, 64),
+    VSTAR(float, LOPE_F32, 4, 64, 16, 256, 64),
+    VSTAR(double, LOPE_F64, 1, 32, 32, 256, 64),
+    VSTAR(double, LOPE_F64, 1, 64, 16, 256, 64),
+    VSTAR(double, LOPE_F64, 2, 32, 32, 256, 64),
+    VSTAR(double, LOPE_F64, 3, 32, 32, 256, 64),
+    VSTAR(double, LOPE_F64, 4, 32, 32, 256, 64),
+};
+
+}  // namespace
+
+int star3d_vec_variants(const Variant** out) {
+    *out = kStar3dVec;
+    return (int)(sizeof(kStar3dVec) / sizeof(kStar3dVec[0]));
+}
+
+}  // namespace lope

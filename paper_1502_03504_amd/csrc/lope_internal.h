@@ -57,7 +57,7 @@ hipError_t launch_accumulate(const DevGrid& part, int part_dtype, const DevGrid&
 hipError_t launch_gbar(const SweepJob& j, double* out, hipStream_t s);
 
 // Tuned kernel families.
-enum Family { FAM_GENERIC = 0, FAM_STAR3D = 1, FAM_PLANE2D = 2 };
+enum Family { FAM_GENERIC = 0, FAM_STAR3D = 1, FAM_PLANE2D = 2, FAM_STAR3D_VEC = 3 };
 
 typedef hipError_t (*VariantFn)(const SweepJob& j, int chunk, hipStream_t s);
 
@@ -73,6 +73,7 @@ struct Variant {
 
 // Registries filled by each kernel file.
 int star3d_variants(const Variant** out);
+int star3d_vec_variants(const Variant** out);
 int plane2d_variants(const Variant** out);
 
 // Variable-coefficient diffusion.
