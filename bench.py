@@ -29,6 +29,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measure_traffic_table():
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def measured_traffic(kernel, n, sweeps):
+    """HBM bytes per launch from the committed counter runs (FETCH_SIZE and
+    WRITE_SIZE, scaled by a known-size copy), if they were taken on this very
+    kernel variant and workload; else None."""
+    import hashlib
+    key = "%s|heat3d_7pt_%d^3_f32_periodic" % (kernel, n)
+    rec = measure_traffic_table().get(key)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["kernel_source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernel_source_sha256"]:
+        return None          # the kernel changed since the counters were taken
+    return rec["traffic_bytes_per_launch"]
+
+
 def measure_adjoint(n=256, steps=200, every=20):
     """Per-step forward / reverse kernel times of the variable-coefficient
     diffusion step (256^3 float32, periodic), and the end-to-end checkpointed
@@ -88,6 +111,45 @@ def measure_adjoint(n=256, steps=200, every=20):
             "ratio_end_to_end": round((t2 - t1) / (t1 - t0), 3)}
 
 
+def measure_batch(reps=3):
+    """512 uneven 2D float32 grids, 50 sweeps each: the batched launches against
+    one launch per grid per sweep (median of reps, HIP events)."""
+    import numpy as np
+    import torch
+
+    import paper_1502_03504_amd as L
+    import synth
+
+    grids, steps = synth.case_batch()
+    entries = [(L.Grid.from_array(g.field, 1), L.Grid.allocate(g.field.shape, 1, torch.float32), g.stencil, g.bc)
+               for g in grids]
+    points = sum(int(g.field.size) for g in grids)
+    plan = L.BatchPlan(entries, steps)
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    tb = timed(plan.apply)
+    tp = timed(plan.apply_per_grid)
+    plan.close()
+    upd = points * steps
+    return {"workload": "batch_512_grids_2d_f32_50_sweeps", "points": points, "batched_ms": round(tb, 3),
+            "per_grid_ms": round(tp, 3), "batched_GPts": round(upd / (tb * 1e-3) / 1e9, 1),
+            "per_grid_GPts": round(upd / (tp * 1e-3) / 1e9, 1), "speedup": round(tp / tb, 2),
+            "launches_batched": steps, "launches_per_grid": steps * len(grids)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +165,7 @@ def main():
                     help="before timing, run one plain device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-grids measurement")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -174,6 +237,11 @@ def main():
         torch.cuda.empty_cache()
         adjoint = measure_adjoint()
         log("adjoint:", adjoint)
+    batch = None
+    if not args.no_batch:
+        torch.cuda.empty_cache()
+        batch = measure_batch()
+        log("batch:", batch)
 
     cpu = None
     if args.cpu_sweeps > 0:
@@ -204,9 +272,10 @@ def main():
         "config": {"workload": "heat3d_7pt_%d^3_f32_periodic_%d_sweeps" % (n, sweeps), "grid": [n, n, n],
                    "sweeps_per_step": sweeps, "halo": 1, "kernel": info.split()[0], "sweeps_per_pass": td},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(info.split()[0], n, sweeps)},
         "cpu_baseline": cpu,
         "adjoint_forward": adjoint,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 

@@ -266,9 +266,12 @@ int lope_variant_info(int id, char* text, int cap);
  * sweeps (0 = automatic) on this grid/stencil, or a negative status. */
 int lope_select_variant(const lope_grid* g, const lope_stencil* st, int32_t tdepth);
 
-/* Register an automatic choice: for grids and stencils like (g, st), use
- * tune->variant, tune->tdepth and tune->chunk.  The key is (ndim, radius,
- * dtype, star/box shape, size bucket = floor(log2(interior points))). */
+/* Register a launch choice for grids and stencils like (g, st): use
+ * tune->variant and tune->chunk.  tune->tdepth says which request it answers:
+ * 0 = lope_iterate with tdepth 0 (automatic), k = lope_iterate with tdepth k
+ * (then the variant's own depth must be k).  The key is (ndim, radius,
+ * dtype, star/box shape, size bucket = floor(log2(interior points)),
+ * requested depth).  Only structural checks are made (no device access). */
 int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning* tune);
 
 #ifdef __cplusplus

@@ -241,12 +241,14 @@ struct TuneChoice {
     int variant, tdepth, chunk;
 };
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int>, TuneChoice> g_tune;
+typedef std::tuple<int, int, int, int, int, int> TuneKey;
+std::map<TuneKey, TuneChoice> g_tune;
 
-std::tuple<int, int, int, int, int> tune_key(int ndim, int radius, int dtype, bool star, int64_t points) {
+// (ndim, radius, dtype, star, floor(log2 points), requested sweeps per pass; 0 = automatic)
+TuneKey tune_key(int ndim, int radius, int dtype, bool star, int64_t points, int tdepth_req) {
     int bucket = 0;
     while (bucket < 62 && ((int64_t)1 << (bucket + 1)) <= points) ++bucket;
-    return std::make_tuple(ndim, radius, dtype, star ? 1 : 0, bucket);
+    return std::make_tuple(ndim, radius, dtype, star ? 1 : 0, bucket, tdepth_req);
 }
 
 bool variant_fits(const Variant& v, const SweepJob& j, int tdepth) {
@@ -309,20 +311,19 @@ Plan choose(const SweepJob& j, int tdepth_req, int variant_req, int chunk_req) {
         return p;
     }
     int td = tdepth_req;
-    if (td <= 0) {
+    {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const int64_t pts = (int64_t)j.src.nx * j.src.ny * j.src.nz;
-        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts));
-        if (it != g_tune.end()) {
+        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts, td > 0 ? td : 0));
+        if (it != g_tune.end() && it->second.variant > 0 &&
+            variant_fits(registry().v[it->second.variant - 1], j, it->second.tdepth)) {
             p.variant = it->second.variant;
             p.tdepth = it->second.tdepth;
             if (p.chunk <= 0) p.chunk = it->second.chunk;
-            if (p.variant > 0 && variant_fits(registry().v[p.variant - 1], j, p.tdepth)) return p;
-            p.variant = 0;
-            p.tdepth = 1;
+            return p;
         }
-        td = 1;
     }
+    if (td <= 0) td = 1;
     for (; td >= 1; --td) {
         const int v = default_variant(j, td);
         if (v) {
@@ -807,9 +808,11 @@ int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning*
     int td = tune->variant > 0 ? registry().v[tune->variant - 1].tdepth : 1;
     if (tune->variant > 0 && !variant_fits(registry().v[tune->variant - 1], job, td))
         return fail(LOPE_ERR_UNSUPPORTED, "variant %d does not fit this grid/stencil", tune->variant);
+    if (tune->tdepth < 0 || tune->tdepth > 4 || (tune->tdepth > 0 && tune->tdepth != td))
+        return fail(LOPE_ERR_INVALID_ARG, "tdepth %d: 0 (automatic) or the variant's own depth %d", tune->tdepth, td);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(job.ndim, job.radius, job.dtype, job.star, (int64_t)job.src.nx * job.src.ny * job.src.nz)] =
-        TuneChoice{tune->variant, td, tune->chunk};
+    g_tune[tune_key(job.ndim, job.radius, job.dtype, job.star, (int64_t)job.src.nx * job.src.ny * job.src.nz,
+                    tune->tdepth)] = TuneChoice{tune->variant, td, tune->chunk};
     return LOPE_OK;
 }
 

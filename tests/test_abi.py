@@ -222,3 +222,29 @@ def test_variant_selection_and_tuning_table():
     assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0) == v2
     box, _kb = stencil(ndim=3, r=1, fill=0.1)                            # 3D box: generic kernel
     assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(box), 1) == 0
+
+
+def test_tune_cache_registration(tmp_path):
+    """Cached choices are keyed by variant name and requested depth and reach
+    the library's table without a device."""
+    import json
+    import paper_1502_03504_amd as P
+    from paper_1502_03504_amd import tune
+    names = {f["name"]: vid for vid, f in tune._variant_table().items()}
+    t1 = [n for n in names if n.startswith("star3d_float_r1_t1_")][0]
+    t2 = [n for n in names if n.startswith("star3d_float_r1_t2_")][0]
+    cache = {"gfx950|3|1|f32|star|18|0": {"variant": t2, "tdepth": 2, "chunk": 16, "gpts": 1.0},
+             "gfx950|3|1|f32|star|18|1": {"variant": t1, "tdepth": 1, "chunk": 8, "gpts": 1.0},
+             "gfx950|3|1|f32|star|18|3": {"variant": "no_such_variant", "tdepth": 3, "chunk": 8, "gpts": 1.0}}
+    path = tmp_path / "cache.json"
+    path.write_text(json.dumps(cache))
+    assert tune.register_cache(str(path)) == 2
+    s, _keep = stencil(ndim=3, r=1, fill=0.0)
+    _keep[13] = 0.4
+    for i in (4, 10, 12, 14, 16, 22):
+        _keep[i] = 0.1
+    g = grid(n=(64, 64, 64))          # 2^18 points: bucket 18
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0) == names[t2]
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 1) == names[t1]
+    bad = _lib.lope_tuning(names[t2], 1, 0, 0)       # depth 1 request answered by a depth-2 variant
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(bad)) == _lib.LOPE_ERR_INVALID_ARG
