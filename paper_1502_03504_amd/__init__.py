@@ -140,14 +140,15 @@ class Grid:
         return {1: (1,), 2: (self.sy, 1), 3: (self.sz, self.sy, 1)}[self.ndim]
 
     def interior(self) -> torch.Tensor:
-        return self.storage.as_strided(self.shape, self._strides(), self.offset)
+        # as_strided offsets count from the start of the underlying storage
+        return self.storage.as_strided(self.shape, self._strides(), self.storage.storage_offset() + self.offset)
 
     def padded(self) -> torch.Tensor:
         h = self.h
         shp = tuple(s + 2 * h for s in self.shape)
         d = self.ndim
         off = self.offset - h - (h * self.sy if d >= 2 else 0) - (h * self.sz if d >= 3 else 0)
-        return self.storage.as_strided(shp, self._strides(), off)
+        return self.storage.as_strided(shp, self._strides(), self.storage.storage_offset() + off)
 
     def numpy(self) -> np.ndarray:
         return self.interior().detach().cpu().numpy().copy()

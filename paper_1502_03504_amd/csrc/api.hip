@@ -530,8 +530,10 @@ int lope_apply_var(const lope_grid* src, const lope_grid* dst, const lope_varcoe
     if ((rc = check_memory(src, "src")) || (rc = check_memory(dst, "dst")) || (rc = check_memory(vc->kappa, "kappa")))
         return rc;
     if (is_empty(src)) return LOPE_OK;
-    const hipError_t e = launch_var_forward(dev_grid(src), dev_grid(dst), dev_grid(vc->kappa), src->dtype, vc->dt,
-                                            (hipStream_t)stream);
+    const DevGrid gs[3] = {dev_grid(src), dev_grid(dst), dev_grid(vc->kappa)};
+    const hipError_t e = var_vec_fits(gs, 3, src->dtype)
+                             ? launch_var_forward_vec(gs[0], gs[1], gs[2], src->dtype, vc->dt, (hipStream_t)stream)
+                             : launch_var_forward(gs[0], gs[1], gs[2], src->dtype, vc->dt, (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion launch");
 }
 
@@ -564,9 +566,14 @@ int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, cons
         (rc = check_memory(gkappa, "gkappa")))
         return rc;
     if (is_empty(lam_next)) return LOPE_OK;
+    const DevGrid gs[5] = {dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(vc->kappa), dev_grid(gkappa)};
+    const bool vec = var_vec_fits(gs, 4, lam_next->dtype) &&
+                     (gkappa->dtype != lam_next->dtype || var_vec_fits(gs + 4, 1, gkappa->dtype));
     const hipError_t e =
-        launch_var_adjoint(dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(vc->kappa), dev_grid(gkappa),
-                           lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream);
+        vec ? launch_var_adjoint_vec(gs[0], gs[1], gs[2], gs[3], gs[4], lam_next->dtype, gkappa->dtype, vc->dt,
+                                     (hipStream_t)stream)
+            : launch_var_adjoint(gs[0], gs[1], gs[2], gs[3], gs[4], lam_next->dtype, gkappa->dtype, vc->dt,
+                                 (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion adjoint launch");
 }
 

@@ -83,6 +83,15 @@ hipError_t launch_var_adjoint(const DevGrid& lam_next, const DevGrid& lam, const
                               const DevGrid& kappa, const DevGrid& gk, int dtype, int gk_dtype,
                               double dt, hipStream_t s);
 
+// 16-byte vector variants of the diffusion kernels; usable when every grid
+// has a 16-byte aligned origin and y/z strides in whole vectors.
+bool var_vec_fits(const DevGrid* gs, int count, int dtype);
+hipError_t launch_var_forward_vec(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, int dtype,
+                                  double dt, hipStream_t s);
+hipError_t launch_var_adjoint_vec(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u,
+                                  const DevGrid& kappa, const DevGrid& gk, int dtype, int gk_dtype, double dt,
+                                  hipStream_t s);
+
 // Batched persistent sweeps (tables built by the ABI layer, read by the kernel).
 struct BatchGrid {
     DevGrid src, dst;

@@ -29,6 +29,24 @@ def grid_from(arr: np.ndarray, h: int, fill=0.0) -> L.Grid:
     return g
 
 
+def packed_grid_from(arr: np.ndarray, h: int) -> L.Grid:
+    """A grid with tightly packed padded rows (lead = h, row pitch nx + 2h):
+    origins and strides are generally not 16-byte multiples, which forces the
+    scalar kernels."""
+    tdt = torch.float64 if arr.dtype == np.float64 else torch.float32
+    shape = arr.shape
+    d = len(shape)
+    nx = shape[-1]
+    sy = nx + 2 * h
+    rows = shape[-2] + 2 * h if d >= 2 else 1
+    sz = sy * rows
+    planes = shape[-3] + 2 * h if d >= 3 else 1
+    storage = torch.zeros(sz * planes + 1, dtype=tdt, device="cuda")[1:]     # shift by one element
+    g = L.Grid(storage, shape, h, h, sy, sz)
+    g.interior().copy_(torch.from_numpy(np.ascontiguousarray(arr)).cuda())
+    return g
+
+
 def empty_grid(shape, h: int, dtype, fill=0.0) -> L.Grid:
     tdt = torch.float64 if np.dtype(dtype) == np.float64 else torch.float32
     return L.Grid.allocate(shape, h, tdt, "cuda", fill=fill)

@@ -224,6 +224,25 @@ def test_variant_selection_and_tuning_table():
     assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(box), 1) == 0
 
 
+def test_grid_views_match_descriptor():
+    """Grid views and the descriptor handed to the library address the same
+    elements, also for storage that starts at a non-zero offset."""
+    import torch
+    import paper_1502_03504_amd as P
+    st = torch.zeros(12 * 11 * 10 + 1)[1:]
+    g = P.Grid(st, (8, 9, 10), 1, 1, 12, 132)
+    d = g.descriptor()
+    assert g.interior().data_ptr() == d.origin
+    assert g.padded().data_ptr() == d.origin - 4 * (1 + 12 + 132)
+    assert (d.n[0], d.n[1], d.n[2], d.stride[1], d.stride[2]) == (10, 9, 8, 12, 132)
+    a = P.Grid.allocate((5, 6, 7), 2, torch.float64, "cpu")
+    assert a.interior().data_ptr() == a.descriptor().origin
+    # the interior row start sits 128 bytes past a 128-byte multiple of the storage start
+    assert (a.descriptor().origin - a.storage.data_ptr()) % 128 == 0
+    with pytest.raises(ValueError):
+        P.Grid(torch.zeros(100), (8, 9, 10), 1, 1, 12, 132)
+
+
 def test_tune_cache_registration(tmp_path):
     """Cached choices are keyed by variant name and requested depth and reach
     the library's table without a device."""

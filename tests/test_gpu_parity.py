@@ -12,7 +12,7 @@ import oracle
 import paper_1502_03504_amd as L
 import synth
 from synth import DIRICHLET as D, PERIODIC as P
-from tests.gpu_util import empty_grid, grid_from, halo_mask, rel_err, tol, variants_for
+from tests.gpu_util import empty_grid, grid_from, halo_mask, packed_grid_from, rel_err, tol, variants_for
 
 pytestmark = pytest.mark.gpu
 
@@ -161,15 +161,19 @@ def test_adjoint_matches_oracle(ndim, r, shape_kind, dtype):
         assert abs(gb.item() - gw) <= 1e-9 * max(1.0, abs(gw)), (gb.item(), gw)
 
 
+@pytest.mark.parametrize("packed", [False, True])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_diffusion_forward_and_reverse(dtype):
+def test_diffusion_forward_and_reverse(dtype, packed):
+    """Aligned grids take the vector kernels, packed (misaligned) grids the
+    scalar ones; both against the oracle."""
     rng = np.random.default_rng([synth.CFG_TEST, 300])
     shape = (21, 35, 70)
     u = rng.uniform(0, 1, shape).astype(dtype)
     k = rng.uniform(0.05, 0.2, shape).astype(dtype)
     lam = rng.standard_normal(shape).astype(dtype)
     dt = 0.1
-    ug, kg = grid_from(u, 1), grid_from(k, 1)
+    mk = packed_grid_from if packed else grid_from
+    ug, kg = mk(u, 1), mk(k, 1)
     out = empty_grid(shape, 1, dtype)
     L.lope_apply_var(ug, out, kg, dt, (P, P, P))
     assert rel_err(out.numpy(), oracle.diffusion_step(u, k, dt)) <= tol(dtype)
@@ -182,6 +186,21 @@ def test_diffusion_forward_and_reverse(dtype):
         want_g = 0.5 + oracle.diffusion_kappa_vjp(u, lam, dt)
         assert rel_err(lam_out.numpy(), want_l) <= tol(dtype)
         assert rel_err(gk.numpy() - 0.5, want_g - 0.5) <= 10 * tol(gdt if gdt == np.float32 else dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("r", [1, 4])
+def test_packed_grids_take_scalar_kernels(r, dtype):
+    """Misaligned grids fall back from the vector kernels and still match."""
+    rng = np.random.default_rng([synth.CFG_TEST, 500 + r])
+    st = synth.contractive(synth.random_stencil(rng, 3, r, "star"))
+    u = _field((19, 37, 70), dtype, 11)
+    for kinds in BCS[3][:2]:
+        a = packed_grid_from(u, r)
+        b = packed_grid_from(np.zeros_like(u), r)
+        idx = L.lope_iterate(a, b, st, (kinds, 0.3), 3, tdepth=1)
+        want = oracle.iterate(u, st.coeffs, kinds, 0.3, 3)
+        assert rel_err((a, b)[idx].numpy(), want) <= tol(dtype) * 3
 
 
 def test_accumulate():
