@@ -87,7 +87,9 @@ def measure_adjoint(n=256, steps=200, every=20):
         return ts[len(ts) // 2]
 
     fwd = timed(lambda: L.lope_apply_var(u, v, kap, c.dt, bc))
-    adj = timed(lambda: L.lope_apply_var_adjoint(lam, lam2, u, kap, c.dt, bc, g32))
+    adj1 = timed(lambda: L.lope_apply_var_adjoint(lam, lam2, u, kap, c.dt, bc, g32))
+    # the reverse sweep runs step pairs fused: per-step time = pass time / 2
+    adj = timed(lambda: L.lope_apply_var_adjoint2(lam, lam2, u, v, kap, c.dt, bc, g32)) / 2.0
     u0 = torch.from_numpy(c.u0).cuda()
     k0 = torch.from_numpy(c.kappa).cuda()
     tg = torch.from_numpy(c.target).cuda()
@@ -106,7 +108,10 @@ def measure_adjoint(n=256, steps=200, every=20):
     return {"workload": "diffusion_7pt_varcoef_%d^3_f32_periodic_%d_steps_checkpoint_%d" % (n, steps, every),
             "fwd_ms_per_step": round(fwd, 4), "adj_ms_per_step": round(adj, 4),
             "ratio_per_step": round(adj / fwd, 3),
-            "fwd_GBs": round(12.0 * pts / (fwd * 1e-3) / 1e9, 1), "adj_GBs": round(24.0 * pts / (adj * 1e-3) / 1e9, 1),
+            "adj_single_step_ms": round(adj1, 4), "ratio_single_step": round(adj1 / fwd, 3),
+            "fwd_GBs": round(12.0 * pts / (fwd * 1e-3) / 1e9, 1),
+            "adj_pair_GBs": round(28.0 * pts / (2 * adj * 1e-3) / 1e9, 1),
+            "adj_single_GBs": round(24.0 * pts / (adj1 * 1e-3) / 1e9, 1),
             "fwd_total_ms": round((t1 - t0) * 1e3, 2), "bwd_total_ms": round((t2 - t1) * 1e3, 2),
             "ratio_end_to_end": round((t2 - t1) / (t1 - t0), 3)}
 

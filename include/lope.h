@@ -204,6 +204,16 @@ int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, cons
                            const lope_varcoef* vc, const lope_bc* bc, const lope_grid* gkappa,
                            void* stream);
 
+/* Two reverse steps in one pass: from lam_next = dL/du_{t+1}, the states u_t
+ * and u_tm1 = u_{t-1}, produce lam = dL/du_{t-1} (= the step matrix applied
+ * twice) and add both steps' kappa terms (at u_t with lam_next, and at
+ * u_{t-1} with the intermediate dL/du_t) to gkappa in one update.  Same
+ * validation and restrictions as lope_apply_var_adjoint; lam must not overlap
+ * any input, gkappa must not overlap anything. */
+int lope_apply_var_adjoint2(const lope_grid* lam_next, const lope_grid* lam, const lope_grid* u_t,
+                            const lope_grid* u_tm1, const lope_varcoef* vc, const lope_bc* bc,
+                            const lope_grid* gkappa, void* stream);
+
 /* total (F64) += partial (F32 or F64) over the interior, then partial = 0. */
 int lope_accumulate(const lope_grid* partial, const lope_grid* total, void* stream);
 

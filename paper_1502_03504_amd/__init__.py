@@ -282,6 +282,16 @@ def lope_apply_var_adjoint(lam_next: Grid, lam: Grid, u_t: Grid, kappa: Grid, dt
                                         _stream(stream)))
 
 
+def lope_apply_var_adjoint2(lam_next: Grid, lam: Grid, u_t: Grid, u_tm1: Grid, kappa: Grid, dt: float, bc,
+                            gkappa: Grid, stream=None) -> None:
+    """Two reverse steps in one pass: lam = dL/du_{t-1} from lam_next = dL/du_{t+1}."""
+    kd, vc = _varcoef(kappa, dt)
+    a, b, u, v, g = (lam_next.descriptor(), lam.descriptor(), u_t.descriptor(), u_tm1.descriptor(),
+                     gkappa.descriptor())
+    check(load().lope_apply_var_adjoint2(_ref(a), _ref(b), _ref(u), _ref(v), _ref(vc), _ref(_bc(bc, 3)), _ref(g),
+                                         _stream(stream)))
+
+
 def lope_accumulate(partial: Grid, total: Grid, stream=None) -> None:
     a, b = partial.descriptor(), total.descriptor()
     check(load().lope_accumulate(_ref(a), _ref(b), _stream(stream)))

@@ -92,6 +92,8 @@ SIGNATURES = {
     "lope_apply_var": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_varcoef), P(lope_bc), c_void_p]),
     "lope_apply_var_adjoint": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_grid), P(lope_varcoef),
                                               P(lope_bc), P(lope_grid), c_void_p]),
+    "lope_apply_var_adjoint2": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_grid), P(lope_grid),
+                                               P(lope_varcoef), P(lope_bc), P(lope_grid), c_void_p]),
     "lope_accumulate": (ctypes.c_int, [P(lope_grid), P(lope_grid), c_void_p]),
     "lope_batch_plan_create": (ctypes.c_int, [P(lope_batch_item), ctypes.c_int64, ctypes.c_int64, c_void_p,
                                               P(c_void_p)]),

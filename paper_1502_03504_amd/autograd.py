@@ -9,23 +9,28 @@ returns dL/du0 and dL/dkappa:
   checkpoint_every), so memory grows with n_steps / k, not n_steps;
 * the backward pass walks the segments in reverse; for each it recomputes the
   segment's states from its checkpoint with the forward kernel, then runs the
-  reverse kernel from the segment's last step down to its first, which turns
-  lambda_{t+1} = dL/du_{t+1} into lambda_t and adds the step's kappa
-  derivative into a float32 accumulator;
+  reverse kernels from the segment's last step down to its first, which turn
+  lambda_{t+1} = dL/du_{t+1} into lambda_t and add each step's kappa
+  derivative into a float32 accumulator.  Steps (2m+1, 2m) that lie in one
+  segment run as one fused two-step pass (lope_apply_var_adjoint2), the rest
+  one step at a time;
 * every FOLD_EVERY steps (at t divisible by it) the float32 accumulator is
   folded into a float64 total (lope_accumulate), so the kappa gradient is
   reduced in float64 over the time loop.
 
-Recomputation is deterministic (same kernels, same inputs) and the folds sit
-at fixed time indices, so the gradient is bit-for-bit independent of the
-checkpoint interval.  Everything runs on the current
+Recomputation is deterministic (same kernels, same inputs), the fused pass
+computes every lambda_t exactly as the one-step kernel does, and the folds sit
+at fixed time indices.  So dL/du0 is bit-for-bit independent of the
+checkpoint interval; dL/dkappa is too for every even interval (all pairs
+fused), while an odd interval splits some pairs and changes only the rounding
+of the kappa accumulator.  Everything runs on the current
 stream; nothing synchronises with the host.
 """
 from __future__ import annotations
 
 import torch
 
-from . import Grid, lope_accumulate, lope_apply_var, lope_apply_var_adjoint
+from . import Grid, lope_accumulate, lope_apply_var, lope_apply_var_adjoint, lope_apply_var_adjoint2
 
 _PERIODIC = (("periodic",) * 3, 0.0)
 FOLD_EVERY = 20
@@ -77,10 +82,20 @@ class DiffusionFunction(torch.autograd.Function):
             seg_states[0].interior().copy_(checkpoints[s].interior())
             for i in range(1, length):
                 lope_apply_var(seg_states[i - 1], seg_states[i], kap, dt, _PERIODIC)
-            for i in range(length - 1, -1, -1):
-                lope_apply_var_adjoint(lam, lam2, seg_states[i], kap, dt, _PERIODIC, g32)
+            i = length - 1
+            while i >= 0:
+                t = t0 + i
+                if t % 2 == 1 and i >= 1:
+                    # steps t and t-1 fused (pairs sit at absolute indices (2m+1, 2m))
+                    lope_apply_var_adjoint2(lam, lam2, seg_states[i], seg_states[i - 1], kap, dt, _PERIODIC, g32)
+                    low = t - 1
+                    i -= 2
+                else:
+                    lope_apply_var_adjoint(lam, lam2, seg_states[i], kap, dt, _PERIODIC, g32)
+                    low = t
+                    i -= 1
                 lam, lam2 = lam2, lam
-                if (t0 + i) % FOLD_EVERY == 0:
+                if low % FOLD_EVERY == 0:
                     lope_accumulate(g32, g64)
         grad_u0 = lam.interior().clone()
         grad_kappa = g64.interior().to(grad_out.dtype)

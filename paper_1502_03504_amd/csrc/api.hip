@@ -226,6 +226,8 @@ struct Registry {
         const Variant* p;
         int n = star3d_vec_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
+        n = star3d_vtb_variants(&p);
+        for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = star3d_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = plane2d_variants(&p);
@@ -530,10 +532,8 @@ int lope_apply_var(const lope_grid* src, const lope_grid* dst, const lope_varcoe
     if ((rc = check_memory(src, "src")) || (rc = check_memory(dst, "dst")) || (rc = check_memory(vc->kappa, "kappa")))
         return rc;
     if (is_empty(src)) return LOPE_OK;
-    const DevGrid gs[3] = {dev_grid(src), dev_grid(dst), dev_grid(vc->kappa)};
-    const hipError_t e = var_vec_fits(gs, 3, src->dtype)
-                             ? launch_var_forward_vec(gs[0], gs[1], gs[2], src->dtype, vc->dt, (hipStream_t)stream)
-                             : launch_var_forward(gs[0], gs[1], gs[2], src->dtype, vc->dt, (hipStream_t)stream);
+    const hipError_t e = launch_var_forward(dev_grid(src), dev_grid(dst), dev_grid(vc->kappa), src->dtype, vc->dt,
+                                            (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion launch");
 }
 
@@ -566,15 +566,47 @@ int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, cons
         (rc = check_memory(gkappa, "gkappa")))
         return rc;
     if (is_empty(lam_next)) return LOPE_OK;
-    const DevGrid gs[5] = {dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(vc->kappa), dev_grid(gkappa)};
-    const bool vec = var_vec_fits(gs, 4, lam_next->dtype) &&
-                     (gkappa->dtype != lam_next->dtype || var_vec_fits(gs + 4, 1, gkappa->dtype));
-    const hipError_t e =
-        vec ? launch_var_adjoint_vec(gs[0], gs[1], gs[2], gs[3], gs[4], lam_next->dtype, gkappa->dtype, vc->dt,
-                                     (hipStream_t)stream)
-            : launch_var_adjoint(gs[0], gs[1], gs[2], gs[3], gs[4], lam_next->dtype, gkappa->dtype, vc->dt,
-                                 (hipStream_t)stream);
+    const hipError_t e = launch_var_adjoint(dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(vc->kappa),
+                                            dev_grid(gkappa), lam_next->dtype, gkappa->dtype, vc->dt,
+                                            (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion adjoint launch");
+}
+
+int lope_apply_var_adjoint2(const lope_grid* lam_next, const lope_grid* lam, const lope_grid* u_t,
+                            const lope_grid* u_tm1, const lope_varcoef* vc, const lope_bc* bc,
+                            const lope_grid* gkappa, void* stream) {
+    int rc;
+    if (!vc) return fail(LOPE_ERR_INVALID_ARG, "null varcoef");
+    if ((rc = check_grid(lam_next, "lam_next")) || (rc = check_grid(lam, "lam")) || (rc = check_grid(u_t, "u_t")) ||
+        (rc = check_grid(u_tm1, "u_tm1")) || (rc = check_grid(vc->kappa, "kappa")) ||
+        (rc = check_grid(gkappa, "gkappa")) || (rc = check_same(lam_next, lam, "lam_next", "lam")) ||
+        (rc = check_same(lam_next, u_t, "lam_next", "u_t")) || (rc = check_same(lam_next, u_tm1, "lam_next", "u_tm1")) ||
+        (rc = check_same(lam_next, vc->kappa, "lam_next", "kappa")) || (rc = check_bc(bc, lam_next->ndim)))
+        return rc;
+    if (gkappa->ndim != lam_next->ndim || gkappa->n[0] != lam_next->n[0] || gkappa->n[1] != lam_next->n[1] ||
+        gkappa->n[2] != lam_next->n[2])
+        return fail(LOPE_ERR_INVALID_ARG, "gkappa extents differ");
+    if (lam_next->ndim != 3) return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion is 3D only");
+    for (int a = 0; a < 3; ++a)
+        if (bc->kind[a] != LOPE_BC_PERIODIC)
+            return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion supports periodic boundaries only");
+    if (lam_next->h < 1 || u_t->h < 1 || u_tm1->h < 1 || vc->kappa->h < 1)
+        return fail(LOPE_ERR_HALO_TOO_SMALL, "lam_next, u_t, u_tm1 and kappa need h >= 1");
+    const lope_grid* ins[4] = {lam_next, u_t, u_tm1, vc->kappa};
+    const char* names[4] = {"lam_next", "u_t", "u_tm1", "kappa"};
+    for (int i = 0; i < 4; ++i)
+        if ((rc = check_alias(ins[i], lam, names[i], "lam")) || (rc = check_alias(ins[i], gkappa, names[i], "gkappa")))
+            return rc;
+    if ((rc = check_alias(gkappa, lam, "gkappa", "lam"))) return rc;
+    if ((rc = device_ready())) return rc;
+    for (int i = 0; i < 4; ++i)
+        if ((rc = check_memory(ins[i], names[i]))) return rc;
+    if ((rc = check_memory(lam, "lam")) || (rc = check_memory(gkappa, "gkappa"))) return rc;
+    if (is_empty(lam_next)) return LOPE_OK;
+    const hipError_t e = launch_var_adjoint2(dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(u_tm1),
+                                             dev_grid(vc->kappa), dev_grid(gkappa), lam_next->dtype, gkappa->dtype,
+                                             vc->dt, (hipStream_t)stream);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion two-step adjoint launch");
 }
 
 int lope_accumulate(const lope_grid* partial, const lope_grid* total, void* stream) {

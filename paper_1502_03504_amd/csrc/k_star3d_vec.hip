@@ -6,9 +6,9 @@
 // (the z neighbours).  The centre plane of the tile plus its x/y halo
 // (R rows above and below, R columns left and right; the star needs no
 // corners) is published in LDS, double-buffered, one barrier per plane.
-// Core planes are fetched R+1 planes ahead of the plane being computed, the
-// halo of the next centre plane one plane ahead, so the loads of the next
-// step are in flight while this one computes.
+// Core planes are fetched R+2 planes ahead of the plane being computed and
+// halos two planes ahead (two alternating prefetch buffers), so the loads of
+// the next two steps are in flight while this one computes.
 //
 // The LDS row holds the core at a 16-byte aligned column (kLead) so the
 // centre and y-neighbour rows are read as vectors.  Every point is summed as
@@ -179,9 +179,10 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
     };
 
     T ring[RPT][RING][VEC];
-    T pre[RPT][VEC];
-    T hpre[HPT][VEC];
-    // prologue: planes z0-R .. z0+R into the ring, centre plane z0 into LDS[0]
+    T preA[RPT][VEC], preB[RPT][VEC];
+    T hA[HPT][VEC], hB[HPT][VEC];
+    // prologue: planes z0-R .. z0+R into the ring, centre plane z0 into LDS[0],
+    // then the next two core planes and halos in flight
 #pragma unroll
     for (int s = 0; s < RING; ++s) {
         T tmp[RPT][VEC];
@@ -191,20 +192,24 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
 #pragma unroll
             for (int e = 0; e < VEC; ++e) ring[k][s][e] = tmp[k][e];
     }
-    load_halo(z0, hpre);
-    store_halo(lds[0], hpre);
+    load_halo(z0, hA);
+    store_halo(lds[0], hA);
 #pragma unroll
     for (int k = 0; k < RPT; ++k)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) lds[0][R + ty + k * TYT][kLead + tx * VEC + e] = ring[k][R][e];
-    load_core(z0 + R + 1, pre);
-    load_halo(z0 + 1, hpre);
+    load_core(z0 + R + 1, preA);
+    load_halo(z0 + 1, hA);
+    load_core(z0 + R + 2, preB);
+    load_halo(z0 + 2, hB);
     lds_barrier();
 
-    for (int zc = z0; zc < zend; ++zc) {
+    // One march step: compute plane zc, shift in core plane zc+R+1 (held in
+    // pre), publish plane zc+1 (halo in hp), then refill pre/hp with the
+    // planes two steps ahead.  Steps alternate between two prefetch buffers.
+    auto step = [&](int zc, T (&pre)[RPT][VEC], T (&hp)[HPT][VEC]) {
         const int buf = (zc - z0) & 1;
         T (*L)[LW] = lds[buf];
-        // compute plane zc
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
             const int ly = R + ty + k * TYT;
@@ -239,7 +244,6 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
                 }
             }
         }
-        // advance: shift the ring, publish plane zc+1 in the other buffer
 #pragma unroll
         for (int k = 0; k < RPT; ++k)
 #pragma unroll
@@ -250,15 +254,21 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
             }
         if (zc + 1 < zend) {
             T (*N)[LW] = lds[buf ^ 1];
-            store_halo(N, hpre);
+            store_halo(N, hp);
 #pragma unroll
             for (int k = 0; k < RPT; ++k)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) N[R + ty + k * TYT][kLead + tx * VEC + e] = ring[k][R][e];
-            if (zc + 2 < zend) load_core(zc + R + 2, pre);
-            if (zc + 2 < zend) load_halo(zc + 2, hpre);
+            if (zc + 2 < zend) {
+                load_core(zc + R + 3, pre);
+                load_halo(zc + 3, hp);
+            }
         }
         lds_barrier();
+    };
+    for (int zc = z0; zc < zend; zc += 2) {
+        step(zc, preA, hA);
+        if (zc + 1 < zend) step(zc + 1, preB, hB);
     }
 }
 

@@ -74,6 +74,7 @@ struct Variant {
 // Registries filled by each kernel file.
 int star3d_variants(const Variant** out);
 int star3d_vec_variants(const Variant** out);
+int star3d_vtb_variants(const Variant** out);
 int plane2d_variants(const Variant** out);
 
 // Variable-coefficient diffusion.
@@ -83,14 +84,10 @@ hipError_t launch_var_adjoint(const DevGrid& lam_next, const DevGrid& lam, const
                               const DevGrid& kappa, const DevGrid& gk, int dtype, int gk_dtype,
                               double dt, hipStream_t s);
 
-// 16-byte vector variants of the diffusion kernels; usable when every grid
-// has a 16-byte aligned origin and y/z strides in whole vectors.
-bool var_vec_fits(const DevGrid* gs, int count, int dtype);
-hipError_t launch_var_forward_vec(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, int dtype,
-                                  double dt, hipStream_t s);
-hipError_t launch_var_adjoint_vec(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u,
-                                  const DevGrid& kappa, const DevGrid& gk, int dtype, int gk_dtype, double dt,
-                                  hipStream_t s);
+// Two fused reverse steps: lam_{t-1} from lam_{t+1}, both kappa terms in one update.
+hipError_t launch_var_adjoint2(const DevGrid& lam_next, const DevGrid& lam_out, const DevGrid& u_t,
+                               const DevGrid& u_tm1, const DevGrid& kappa, const DevGrid& gk, int dtype,
+                               int gk_dtype, double dt, hipStream_t s);
 
 // Batched persistent sweeps (tables built by the ABI layer, read by the kernel).
 struct BatchGrid {

@@ -167,9 +167,11 @@ def register_cache(path=None) -> int:
         g.n[0] = 1 << bucket
         g.n[1] = g.n[2] = 1
         g.stride[0] = 1
-        g.stride[1] = (1 << bucket) + 2 * radius
+        # strides and origin in whole 128-byte lines, like Grid.allocate, so
+        # vector variants accept the descriptor
+        g.stride[1] = (((1 << bucket) + 2 * radius + 63) // 64) * 64
         g.stride[2] = g.stride[1] * (1 + 2 * radius)
-        g.origin = 0x1000
+        g.origin = 0x100000
         w = 2 * radius + 1
         import numpy as np
         c = np.zeros((w,) * ndim)

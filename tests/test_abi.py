@@ -243,6 +243,14 @@ def test_grid_views_match_descriptor():
         P.Grid(torch.zeros(100), (8, 9, 10), 1, 1, 12, 132)
 
 
+def test_committed_tuning_table_registers_completely():
+    import json
+    from paper_1502_03504_amd import tune
+    with open(tune.DEFAULT_CACHE) as f:
+        n = len(json.load(f))
+    assert n > 0 and tune.register_cache(tune.DEFAULT_CACHE) == n
+
+
 def test_tune_cache_registration(tmp_path):
     """Cached choices are keyed by variant name and requested depth and reach
     the library's table without a device."""
