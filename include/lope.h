@@ -232,8 +232,8 @@ typedef struct lope_batch_item {
 typedef struct lope_batch_plan lope_batch_plan;
 
 /* Build a plan for n_items grids and n_steps sweeps each: validates every
- * item, cuts every grid into row slabs of about 16K points, and uploads the
- * grid and slab tables (the plan owns this device memory).  The plan borrows
+ * item, cuts every grid into tiles of the 2D marching kernel, and uploads the
+ * grid and tile tables (the plan owns this device memory).  The plan borrows
  * the grids' memory until it is destroyed.  Supports 2D float32 grids up to
  * 2048 columns or float64 grids up to 1024 columns, radius <= 1 stencils, one
  * dtype per batch (else LOPE_ERR_UNSUPPORTED / LOPE_ERR_INVALID_ARG).
@@ -241,18 +241,24 @@ typedef struct lope_batch_plan lope_batch_plan;
 int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_t n_steps,
                            void* stream, lope_batch_plan** out);
 
-/* Advance every grid n_steps sweeps with one launch per sweep covering all
- * slabs of all grids (n_steps launches in total); grid i ends in its src if
- * n_steps is even, else in its dst. */
+/* Advance every grid n_steps sweeps from the state in its src: each launch
+ * covers every tile of every grid and fuses tdepth sweeps (about
+ * n_steps/tdepth launches in total).  lope_batch_result_index tells which
+ * buffer holds the result. */
 int lope_batch_apply(lope_batch_plan* plan, void* stream);
 
 /* Same work as lope_batch_apply as ordinary lope_iterate launches, one per
  * grid per sweep (the baseline the batched launch is compared with). */
 int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream);
 
-/* Synchronise `stream`; *out = 0 when the plan's work completed.  out must
- * not be NULL. */
-int lope_batch_plan_error(lope_batch_plan* plan, void* stream, int* out);
+/* Sweeps fused per launch (1..4, default 2): passes of tdepth sweeps, the
+ * remainder of n_steps in one shorter pass.  Builds the plan's tile table for
+ * the depth if needed (synchronous upload). */
+int lope_batch_plan_set_depth(lope_batch_plan* plan, int32_t tdepth);
+
+/* *out = 0 if lope_batch_apply leaves every grid's state in its src, 1 if in
+ * its dst (the parity of the number of passes).  out must not be NULL. */
+int lope_batch_result_index(const lope_batch_plan* plan, int32_t* out);
 
 /* Release the plan's device memory (the caller synchronises first if the plan
  * may still be running).  NULL is a no-op. */

@@ -1,4 +1,4 @@
-"""Batch plans: many uneven 2D grids swept in one persistent launch."""
+"""Batch plans: many uneven 2D grids swept together, one launch per fused pass."""
 from __future__ import annotations
 
 import ctypes
@@ -10,8 +10,10 @@ from ._lib import check, load
 class BatchPlan:
     """Owns a lope_batch_plan and keeps the grids it borrows alive.
 
-    ``entries`` is a sequence of (src Grid, dst Grid, stencil, bc).  After
-    ``apply`` each grid has advanced ``n_steps`` sweeps; its state is in src
+    ``entries`` is a sequence of (src Grid, dst Grid, stencil, bc).  Each
+    ``apply`` advances every grid ``n_steps`` sweeps starting from its src;
+    ``result(i)`` is the grid holding the outcome.  ``apply_per_grid`` does the
+    same work with one launch per grid per sweep and leaves the outcome in src
     when n_steps is even, else in dst.
     """
 
@@ -38,14 +40,22 @@ class BatchPlan:
     def apply_per_grid(self, stream=None) -> None:
         check(load().lope_batch_apply_per_grid(self.handle, self._stream(stream)))
 
-    def error(self, stream=None) -> int:
-        v = ctypes.c_int(-1)
-        check(load().lope_batch_plan_error(self.handle, self._stream(stream), ctypes.byref(v)))
+    def set_depth(self, tdepth: int) -> None:
+        """Sweeps fused per launch (1..4)."""
+        check(load().lope_batch_plan_set_depth(self.handle, int(tdepth)))
+
+    def result_index(self) -> int:
+        v = ctypes.c_int32(-1)
+        check(load().lope_batch_result_index(self.handle, ctypes.byref(v)))
         return v.value
 
     def result(self, i: int):
-        src, dst = self.entries[i][0], self.entries[i][1]
-        return src if self.n_steps % 2 == 0 else dst
+        """The grid that holds entry i's state after apply()."""
+        return self.entries[i][1] if self.result_index() else self.entries[i][0]
+
+    def per_grid_result(self, i: int):
+        """The grid that holds entry i's state after apply_per_grid()."""
+        return self.entries[i][1] if self.n_steps % 2 else self.entries[i][0]
 
     def close(self) -> None:
         if self.handle is not None and self.handle.value:

@@ -392,7 +392,8 @@ int iterate_impl(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
 
 
 // ---- batch plans ----
-constexpr int64_t kSlabPoints = 16384;
+constexpr int kBatchRows = 64;        // rows per batch tile
+constexpr int kBatchDefaultDepth = 2; // sweeps per pass unless set
 
 struct PlanGrid {
     lope_grid src, dst;
@@ -406,14 +407,15 @@ struct PlanGrid {
 struct lope_batch_plan {
     int dtype = LOPE_F32;
     int64_t n_steps = 0;
-    int nslabs = 0;
     int device = 0;
+    int tdepth = kBatchDefaultDepth;
     std::vector<PlanGrid> grids;
+    std::vector<int64_t> order;       // grids in tile-table order (largest first, dealt to XCD ranges)
     std::vector<SweepJob> jobs;       // per-grid launches (the comparison path)
     std::vector<int> job_variant;
     BatchGrid* d_grids = nullptr;
-    BatchSlab* d_slabs = nullptr;
-    int* d_order = nullptr;
+    BatchItem* d_items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // tile tables per depth
+    int nitems[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -421,9 +423,52 @@ namespace {
 void plan_free(lope_batch_plan* p) {
     if (!p) return;
     if (p->d_grids) (void)hipFree(p->d_grids);
-    if (p->d_slabs) (void)hipFree(p->d_slabs);
-    if (p->d_order) (void)hipFree(p->d_order);
+    for (int d = 0; d < 5; ++d)
+        if (p->d_items[d]) (void)hipFree(p->d_items[d]);
     delete p;
+}
+
+// Tile table for passes of `depth` sweeps: per grid (in plan order), tiles of
+// the narrow width if the whole row fits one, else of the wide width, by
+// chunks of kBatchRows rows.  Built and uploaded once per depth.
+int plan_items(lope_batch_plan* p, int depth) {
+    if (p->d_items[depth]) return LOPE_OK;
+    std::vector<BatchItem> items;
+    for (int64_t gi : p->order) {
+        const lope_grid& g = p->grids[(size_t)gi].src;
+        const int64_t nx = g.n[0], ny = g.n[1];
+        if (nx == 0 || ny == 0) continue;
+        const bool wide = nx > batch_tile_width(depth, false);
+        const int64_t bw = batch_tile_width(depth, wide);
+        for (int64_t y0 = 0; y0 < ny; y0 += kBatchRows)
+            for (int64_t x0 = 0; x0 < nx; x0 += bw) {
+                BatchItem it{};
+                it.grid = (int32_t)gi;
+                it.x0 = (int32_t)x0;
+                it.y0 = (int32_t)y0;
+                it.y1 = (int32_t)std::min(ny, y0 + kBatchRows);
+                it.wide = wide ? 1 : 0;
+                items.push_back(it);
+            }
+    }
+    p->nitems[depth] = (int)items.size();
+    if (items.empty()) return LOPE_OK;
+    hipError_t e = hipMalloc(&p->d_items[depth], items.size() * sizeof(BatchItem));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_items[depth], items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (p->d_items[depth]) (void)hipFree(p->d_items[depth]);
+        p->d_items[depth] = nullptr;
+        p->nitems[depth] = 0;
+        return hip_fail(e, "batch tile table upload");
+    }
+    return LOPE_OK;
+}
+
+// Passes of lope_batch_apply: full passes of tdepth sweeps, then one pass of
+// the remaining n mod tdepth sweeps.
+int64_t plan_passes(const lope_batch_plan* p) {
+    return p->n_steps / p->tdepth + (p->n_steps % p->tdepth ? 1 : 0);
 }
 
 }  // namespace
@@ -678,8 +723,8 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         build_job(p->jobs[(size_t)i], &g.src, &g.dst, &g.st, &g.bc, false);
         p->job_variant[(size_t)i] = default_variant(p->jobs[(size_t)i], 1);
     }
-    // grids dealt to the 8 XCD ranges largest-first, least-loaded; slabs laid
-    // out grid by grid in that order so a grid's slabs get consecutive
+    // grids dealt to the 8 XCD ranges largest-first, least-loaded; the tile
+    // tables list grids range by range, so a grid's tiles get consecutive
     // workgroup ids (one XCD range)
     std::vector<int64_t> order((size_t)n_items);
     for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
@@ -695,59 +740,52 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         qgrids[best].push_back(i);
         load[best] += items[i].src.n[0] * items[i].src.n[1];
     }
+    for (int q = 0; q < kNumXcd; ++q)
+        for (int64_t i : qgrids[q]) p->order.push_back(i);
     std::vector<BatchGrid> hg((size_t)n_items);
-    std::vector<BatchSlab> hs;
-    for (int q = 0; q < kNumXcd; ++q) {
-        for (int64_t i : qgrids[q]) {
-            const PlanGrid& g = p->grids[(size_t)i];
-            const SweepJob& j = p->jobs[(size_t)i];
-            BatchGrid& b = hg[(size_t)i];
-            b.src = dev_grid(&g.src);
-            b.dst = dev_grid(&g.dst);
-            b.rule = dev_rule(&g.bc, 2, false);
-            for (int t = 0; t < 9; ++t) b.c[t] = 0.0;
-            const int r = g.st.radius;
-            for (int oy = -r; oy <= r; ++oy)
-                for (int ox = -r; ox <= r; ++ox) b.c[(ox + 1) + (oy + 1) * 3] = j.dense[(ox + r) + (oy + r) * (2 * r + 1)];
-            b.box = j.star ? 0 : 1;
-            const int64_t nx = g.src.n[0], ny = g.src.n[1];
-            int64_t rows = (kSlabPoints + nx - 1) / (nx > 0 ? nx : 1);
-            if (rows < 4) rows = 4;
-            if (rows > ny) rows = ny;
-            if (rows < 1) rows = 1;
-            const int64_t ns = (nx == 0 || ny == 0) ? 0 : (ny + rows - 1) / rows;
-            b.slab0 = (int32_t)hs.size();
-            b.nslabs = (int32_t)ns;
-            b.rows = (int32_t)rows;
-            for (int64_t k = 0; k < ns; ++k) {
-                BatchSlab sl{};
-                sl.grid = (int32_t)i;
-                sl.y0 = (int32_t)(k * rows);
-                sl.y1 = (int32_t)std::min(ny, (k + 1) * rows);
-                hs.push_back(sl);
-            }
-        }
+    for (int64_t i = 0; i < n_items; ++i) {
+        const PlanGrid& g = p->grids[(size_t)i];
+        const SweepJob& j = p->jobs[(size_t)i];
+        BatchGrid& bg = hg[(size_t)i];
+        bg = BatchGrid{};
+        bg.src = dev_grid(&g.src);
+        bg.dst = dev_grid(&g.dst);
+        bg.rule = dev_rule(&g.bc, 2, false);
+        const int r = g.st.radius;
+        for (int oy = -r; oy <= r; ++oy)
+            for (int ox = -r; ox <= r; ++ox) bg.c[(ox + 1) + (oy + 1) * 3] = j.dense[(ox + r) + (oy + r) * (2 * r + 1)];
+        bg.box = j.star ? 0 : 1;
     }
-    p->nslabs = (int)hs.size();
-    std::vector<int> ho(hs.size());
-    for (size_t k = 0; k < hs.size(); ++k) ho[k] = (int)k;
-    hipError_t e = hipSuccess;
-    const size_t ns = hs.empty() ? 1 : hs.size();
-    const size_t ng = hg.empty() ? 1 : hg.size();
-    if ((e = hipMalloc(&p->d_grids, ng * sizeof(BatchGrid))) != hipSuccess ||
-        (e = hipMalloc(&p->d_slabs, ns * sizeof(BatchSlab))) != hipSuccess ||
-        (e = hipMalloc(&p->d_order, ns * sizeof(int))) != hipSuccess) {
-        plan_free(p);
-        return hip_fail(e, "batch plan allocation");
-    }
-    if ((!hg.empty() && (e = hipMemcpy(p->d_grids, hg.data(), hg.size() * sizeof(BatchGrid), hipMemcpyHostToDevice)) != hipSuccess) ||
-        (!hs.empty() && (e = hipMemcpy(p->d_slabs, hs.data(), hs.size() * sizeof(BatchSlab), hipMemcpyHostToDevice)) != hipSuccess) ||
-        (!ho.empty() && (e = hipMemcpy(p->d_order, ho.data(), ho.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)) {
+    hipError_t e = hipMalloc(&p->d_grids, (hg.empty() ? 1 : hg.size()) * sizeof(BatchGrid));
+    if (e == hipSuccess && !hg.empty())
+        e = hipMemcpy(p->d_grids, hg.data(), hg.size() * sizeof(BatchGrid), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
         plan_free(p);
         return hip_fail(e, "batch plan upload");
     }
+    if ((rc = plan_items(p, p->tdepth)) || (n_steps % p->tdepth && (rc = plan_items(p, (int)(n_steps % p->tdepth))))) {
+        plan_free(p);
+        return rc;
+    }
     (void)stream;
     *out = p;
+    return LOPE_OK;
+}
+
+int lope_batch_plan_set_depth(lope_batch_plan* plan, int32_t tdepth) {
+    if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
+    if (tdepth < 1 || tdepth > 4) return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 1..4", tdepth);
+    int rc;
+    if ((rc = device_ready())) return rc;
+    plan->tdepth = tdepth;
+    if ((rc = plan_items(plan, tdepth))) return rc;
+    if (plan->n_steps % tdepth && (rc = plan_items(plan, (int)(plan->n_steps % tdepth)))) return rc;
+    return LOPE_OK;
+}
+
+int lope_batch_result_index(const lope_batch_plan* plan, int32_t* out) {
+    if (!plan || !out) return fail(LOPE_ERR_INVALID_ARG, "null plan or output");
+    *out = (int32_t)(plan_passes(plan) & 1);
     return LOPE_OK;
 }
 
@@ -755,10 +793,18 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream) {
     if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
     int rc;
     if ((rc = device_ready())) return rc;
-    for (int64_t t = 0; t < plan->n_steps; ++t) {
-        const hipError_t e = launch_batch_step(plan->d_grids, plan->d_slabs, plan->d_order, plan->nslabs, (int)(t & 1),
-                                               plan->dtype, (hipStream_t)stream);
-        if (e != hipSuccess) return hip_fail(e, "batch sweep launch");
+    const int64_t full = plan->n_steps / plan->tdepth;
+    const int rem = (int)(plan->n_steps % plan->tdepth);
+    int64_t pass = 0;
+    for (; pass < full; ++pass) {
+        const hipError_t e = launch_batch_pass(plan->d_grids, plan->d_items[plan->tdepth], plan->nitems[plan->tdepth],
+                                               plan->tdepth, (int)(pass & 1), plan->dtype, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "batch pass launch");
+    }
+    if (rem) {
+        const hipError_t e = launch_batch_pass(plan->d_grids, plan->d_items[rem], plan->nitems[rem], rem,
+                                               (int)(pass & 1), plan->dtype, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "batch pass launch");
     }
     return LOPE_OK;
 }
@@ -780,14 +826,6 @@ int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream) {
         j.src = a;
         j.dst = b;
     }
-    return LOPE_OK;
-}
-
-int lope_batch_plan_error(lope_batch_plan* plan, void* stream, int* out) {
-    if (!plan || !out) return fail(LOPE_ERR_INVALID_ARG, "null plan or output");
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "stream sync");
-    *out = 0;
     return LOPE_OK;
 }
 

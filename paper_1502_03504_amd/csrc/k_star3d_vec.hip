@@ -42,7 +42,7 @@ struct Vec<double> {
     static constexpr int n = 2;
 };
 
-template <typename T, int R, int BX, int BY, int NT>
+template <typename T, int R, int BX, int BY, int NT, int PF>
 __global__ void __launch_bounds__(NT)
 k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chunk, int tiles_x, int tiles_y,
              int nblocks, int nblocks_padded) {
@@ -200,8 +200,10 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
         for (int e = 0; e < VEC; ++e) lds[0][R + ty + k * TYT][kLead + tx * VEC + e] = ring[k][R][e];
     load_core(z0 + R + 1, preA);
     load_halo(z0 + 1, hA);
-    load_core(z0 + R + 2, preB);
-    load_halo(z0 + 2, hB);
+    if constexpr (PF == 2) {
+        load_core(z0 + R + 2, preB);
+        load_halo(z0 + 2, hB);
+    }
     lds_barrier();
 
     // One march step: compute plane zc, shift in core plane zc+R+1 (held in
@@ -259,20 +261,22 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
             for (int k = 0; k < RPT; ++k)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) N[R + ty + k * TYT][kLead + tx * VEC + e] = ring[k][R][e];
-            if (zc + 2 < zend) {
-                load_core(zc + R + 3, pre);
-                load_halo(zc + 3, hp);
+            if (zc + PF < zend) {
+                load_core(zc + R + 1 + PF, pre);
+                load_halo(zc + 1 + PF, hp);
             }
         }
         lds_barrier();
     };
-    for (int zc = z0; zc < zend; zc += 2) {
+    for (int zc = z0; zc < zend; zc += PF) {
         step(zc, preA, hA);
-        if (zc + 1 < zend) step(zc + 1, preB, hB);
+        if constexpr (PF == 2) {
+            if (zc + 1 < zend) step(zc + 1, preB, hB);
+        }
     }
 }
 
-template <typename T, int R, int BX, int BY, int NT>
+template <typename T, int R, int BX, int BY, int NT, int PF>
 hipError_t run_star3d_vec(const SweepJob& j, int chunk, hipStream_t s) {
     VStarCoef<T, R> cf;
     const int r = j.radius;
@@ -291,29 +295,35 @@ hipError_t run_star3d_vec(const SweepJob& j, int chunk, hipStream_t s) {
     if (nb64 > (1ll << 30)) return hipErrorInvalidConfiguration;
     const int nb = (int)nb64;
     const int nbp = padded_block_count(nb);
-    hipLaunchKernelGGL((k_star3d_vec<T, R, BX, BY, NT>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, j.rule, cf, chunk,
+    hipLaunchKernelGGL((k_star3d_vec<T, R, BX, BY, NT, PF>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, j.rule, cf, chunk,
                        tiles_x, tiles_y, nb, nbp);
     return hipGetLastError();
 }
 
-#define VSTAR(T, DT, R, BX, BY, NT, CH)                                                                     \
-    {"star3dv_" #T "_r" #R "_t1_" #BX "x" #BY "_nt" #NT, FAM_STAR3D_VEC, 3, R, 1, DT, 0, BX, BY, NT, CH, \
-     &run_star3d_vec<T, R, BX, BY, NT>}
+#define VSTAR(T, DT, R, BX, BY, NT, PF, CH)                                                                \
+    {"star3dv_" #T "_r" #R "_t1_" #BX "x" #BY "_nt" #NT "_pf" #PF, FAM_STAR3D_VEC, 3, R, 1, DT, 0, BX, BY, NT, \
+     CH, &run_star3d_vec<T, R, BX, BY, NT, PF>}
 
+// PF: planes fetched ahead (1 or 2 prefetch buffers)
 const Variant kStar3dVec[] = {
-    VSTAR(float, LOPE_F32, 1, 64, 32, 256, 64),
-    VSTAR(float, LOPE_F32, 1, 128, 16, 256, 64),
-    VSTAR(float, LOPE_F32, 1, 64, 16, 256, 64),
-    VSTAR(float, LOPE_F32, 1, 128, 32, 512, 64),
-    VSTAR(float, LOPE_F32, 2, 64, 32, 256, 64),
-    VSTAR(float, LOPE_F32, 3, 64, 32, 256, 64),
-    VSTAR(float, LOPE_F32, 4, 64, 32, 256, 64),
-    VSTAR(float, LOPE_F32, 4, 64, 16, 256, 64),
-    VSTAR(double, LOPE_F64, 1, 32, 32, 256, 64),
-    VSTAR(double, LOPE_F64, 1, 64, 16, 256, 64),
-    VSTAR(double, LOPE_F64, 2, 32, 32, 256, 64),
-    VSTAR(double, LOPE_F64, 3, 32, 32, 256, 64),
-    VSTAR(double, LOPE_F64, 4, 32, 32, 256, 64),
+    VSTAR(float, LOPE_F32, 1, 128, 16, 256, 2, 32),
+    VSTAR(float, LOPE_F32, 1, 128, 32, 512, 2, 32),
+    VSTAR(float, LOPE_F32, 1, 64, 32, 256, 2, 64),
+    VSTAR(float, LOPE_F32, 1, 64, 16, 256, 2, 64),
+    VSTAR(float, LOPE_F32, 1, 128, 16, 256, 1, 64),
+    VSTAR(float, LOPE_F32, 1, 128, 32, 512, 1, 32),
+    VSTAR(float, LOPE_F32, 1, 256, 16, 512, 2, 32),
+    VSTAR(float, LOPE_F32, 2, 64, 32, 256, 1, 64),
+    VSTAR(float, LOPE_F32, 3, 64, 32, 256, 1, 64),
+    VSTAR(float, LOPE_F32, 4, 64, 16, 256, 1, 128),
+    VSTAR(float, LOPE_F32, 4, 64, 16, 256, 2, 128),
+    VSTAR(float, LOPE_F32, 4, 128, 16, 512, 1, 128),
+    VSTAR(double, LOPE_F64, 1, 64, 16, 256, 2, 32),
+    VSTAR(double, LOPE_F64, 1, 64, 16, 256, 1, 32),
+    VSTAR(double, LOPE_F64, 1, 32, 32, 256, 1, 32),
+    VSTAR(double, LOPE_F64, 2, 32, 32, 256, 1, 64),
+    VSTAR(double, LOPE_F64, 3, 32, 32, 256, 1, 64),
+    VSTAR(double, LOPE_F64, 4, 32, 32, 256, 1, 64),
 };
 
 }  // namespace

@@ -95,19 +95,22 @@ struct BatchGrid {
     DevRule rule;
     double c[9];          // dense 3x3 table, rounded to the grid dtype, x fastest
     int32_t box;          // 1: all 9 taps; 0: the 5 star taps
-    int32_t slab0;        // first slab id of this grid
-    int32_t nslabs;
-    int32_t rows;         // rows per slab (the last slab may be shorter)
-};
-
-struct BatchSlab {
-    int32_t grid;
-    int32_t y0, y1;       // rows [y0, y1)
     int32_t pad[3];
 };
 
-hipError_t launch_batch_step(const BatchGrid* grids, const BatchSlab* slabs, const int* order, int nslabs,
-                             int parity, int dtype, hipStream_t s);
+// One tile of one grid: output columns [x0, x0 + tile width), rows [y0, y1).
+struct BatchItem {
+    int32_t grid;
+    int32_t x0, y0, y1;
+    int32_t wide;         // 1: 512-wide tile, 0: 256-wide tile
+    int32_t pad;
+};
+
+// Output columns of a batch tile sweeping tdepth times per pass.
+int batch_tile_width(int tdepth, bool wide);
+// One pass of tdepth sweeps over every listed tile; parity 0 reads src, 1 reads dst.
+hipError_t launch_batch_pass(const BatchGrid* grids, const BatchItem* items, int nitems, int tdepth, int parity,
+                             int dtype, hipStream_t s);
 
 // ---- device helpers ----
 __device__ __forceinline__ int wrap_index(int i, int n) {

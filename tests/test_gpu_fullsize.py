@@ -156,7 +156,7 @@ def test_batch_512_grids_matches_per_grid_and_oracle():
     plan.apply_per_grid()
     torch.cuda.synchronize()
     for i in range(len(grids)):
-        assert torch.equal(plan.result(i).interior(), got[i]), i
+        assert torch.equal(plan.per_grid_result(i).interior(), got[i]), i
     order = sorted(range(len(grids)), key=lambda i: grids[i].field.size)
     for i in order[:3]:
         g = grids[i]

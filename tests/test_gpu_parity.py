@@ -255,24 +255,35 @@ def test_batch_matches_per_grid_and_oracle(dtype):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
-    """One launch per sweep over every slab of every grid (no waits between
-    workgroups) against the oracle and against one launch per grid per sweep."""
+    """Batched launches (every tile of every grid per launch, 1..4 sweeps
+    fused) against the oracle and, value for value, against one launch per
+    grid per sweep."""
     rng = np.random.default_rng([synth.CFG_TEST, 401])
     n = 9
-    entries, fields = _batch_entries(rng, 24, dtype)
+    entries, fields = _batch_entries(rng, 24, dtype, lo=3, hi=700)
     plan = L.BatchPlan(entries, n)
-    plan.apply()
-    torch.cuda.synchronize()
-    got = [plan.result(i).numpy() for i in range(len(entries))]
-    for i, (e, u) in enumerate(zip(entries, fields)):
-        want = oracle.iterate(u, e[2].coeffs, e[3][0], e[3][1], n)
-        assert rel_err(got[i], want) <= tol(dtype) * n, i
+    ref = None
+    for depth in (2, 1, 3, 4):
+        for (src, _, _, _), u in zip(entries, fields):
+            src.interior().copy_(torch.from_numpy(u).cuda())
+        plan.set_depth(depth)
+        plan.apply()
+        torch.cuda.synchronize()
+        got = [plan.result(i).numpy() for i in range(len(entries))]
+        if ref is None:
+            ref = got
+            for i, (e, u) in enumerate(zip(entries, fields)):
+                want = oracle.iterate(u, e[2].coeffs, e[3][0], e[3][1], n)
+                assert rel_err(got[i], want) <= tol(dtype) * n, i
+        else:
+            for i in range(len(entries)):
+                np.testing.assert_array_equal(got[i], ref[i], err_msg="depth %d grid %d" % (depth, i))
     for (src, dst, _, _), u in zip(entries, fields):
         src.interior().copy_(torch.from_numpy(u).cuda())
     plan.apply_per_grid()
     torch.cuda.synchronize()
     for i in range(len(entries)):
-        np.testing.assert_array_equal(plan.result(i).numpy(), got[i])
+        np.testing.assert_array_equal(plan.per_grid_result(i).numpy(), ref[i])
     plan.close()
 
 
