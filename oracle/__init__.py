@@ -10,7 +10,8 @@ Everything here is the plain definition of what the method computes, written
 for a reader to check against the paper by eye, in float64 arithmetic with the
 state rounded to the grid dtype after every sweep:
 
-* ``stencil``   — halo rule, sweep, iteration, windowed sampling, adjoint;
+* ``stencil``   — halo rule, sweep, iteration (fixed count or until a
+  convergence test holds), windowed sampling, adjoint;
 * ``diffusion`` — the variable-coefficient diffusion step and its gradient.
 
 Parity status: every function is pinned by tests under ``tests/`` against
@@ -18,7 +19,7 @@ closed forms, invariants, library spectral routines or brute force; none is
 "parity unpinned".
 """
 from .stencil import (  # noqa: F401
-    rule_extend, halo_fill, sweep, iterate, sweep_at, adjoint, result_index,
+    rule_extend, halo_fill, sweep, iterate, iterate_until, sweep_at, adjoint, result_index,
 )
 from .diffusion import (  # noqa: F401
     diffusion_step, diffusion_forward, diffusion_loss, diffusion_gradient,

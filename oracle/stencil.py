@@ -18,7 +18,9 @@ What is computed, and where the paper defines it:
   state at invocation time, y[x] = sum_o c_o * B(u)[x+o] (Jacobi: only the old
   state is read; the new one lives in a second buffer).
 * Iteration (section 3.2, the do-while loop around the sweep and the halo
-  transfer): n sweeps, alternating buffers.
+  transfer): n sweeps, alternating buffers; or, with a convergence test the
+  paper leaves undefined, sweeps until the max-norm change of one sweep,
+  checked every m sweeps, is at most a tolerance.
 * Adjoint: the transpose of the sweep's linear part, obtained by scattering
   each tap (the transpose of the gather), and the derivative with respect to g.
 
@@ -132,6 +134,36 @@ def iterate(u0: np.ndarray, coeffs: np.ndarray, kinds, g: float, n_steps: int) -
     for _ in range(int(n_steps)):
         u = sweep(u, coeffs, kinds, g)
     return u
+
+
+def iterate_until(u0: np.ndarray, coeffs: np.ndarray, kinds, g: float, max_steps: int,
+                  check_every: int, tol: float):
+    """The do-while loop of section 3.2 with a convergence test: sweep until
+    the change made by one sweep is small, or max_steps sweeps are done.
+
+    After every sweep t+1 whose count is a multiple of check_every, the
+    residual max_x |u_{t+1}[x] - u_t[x]| is taken over the interior (float64;
+    the difference of two dtype values, then its magnitude, then the maximum,
+    which does not depend on evaluation order).  The loop stops after the
+    first checked sweep whose residual is <= tol.  Returns (u, steps, residual)
+    with residual the last one computed (nan when none was).  An empty field
+    stops at once with 0 steps.
+    """
+    u = np.array(u0, copy=True)
+    res = float("nan")
+    if u.size == 0:
+        return u, 0, res
+    m = int(check_every)
+    for t in range(int(max_steps)):
+        v = sweep(u, coeffs, kinds, g)
+        if (t + 1) % m == 0:
+            res = float(np.max(np.abs(v.astype(np.float64) - u.astype(np.float64))))
+            u = v
+            if res <= tol:
+                return u, t + 1, res
+        else:
+            u = v
+    return u, int(max_steps), res
 
 
 def result_index(n_steps: int) -> int:
