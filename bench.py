@@ -93,17 +93,19 @@ def measure_adjoint(n=256, steps=200, every=20):
     u0 = torch.from_numpy(c.u0).cuda()
     k0 = torch.from_numpy(c.kappa).cuda()
     tg = torch.from_numpy(c.target).cuda()
-    uu = u0.clone().requires_grad_(True)
-    kk = k0.clone().requires_grad_(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    uT = diffusion(uu, kk, c.dt, steps, every)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    d = uT.double() - tg.double()
-    (d * d).sum().backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    for rep in range(2):          # the first run warms the allocator; the second is timed
+        uu = u0.clone().requires_grad_(True)
+        kk = k0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uT = diffusion(uu, kk, c.dt, steps, every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        d = uT.double() - tg.double()
+        (d * d).sum().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        del uT, d, uu, kk
     pts = n ** 3
     return {"workload": "diffusion_7pt_varcoef_%d^3_f32_periodic_%d_steps_checkpoint_%d" % (n, steps, every),
             "fwd_ms_per_step": round(fwd, 4), "adj_ms_per_step": round(adj, 4),
@@ -145,14 +147,90 @@ def measure_batch(reps=3):
         ts.sort()
         return ts[len(ts) // 2]
 
-    tb = timed(plan.apply)
+    by_depth = {}
+    for td in (1, 2, 3, 4):
+        plan.set_depth(td)
+        by_depth[td] = timed(plan.apply)
+    best = min(by_depth, key=by_depth.get)
+    plan.set_depth(best)
+    tb = by_depth[best]
     tp = timed(plan.apply_per_grid)
     plan.close()
     upd = points * steps
-    return {"workload": "batch_512_grids_2d_f32_50_sweeps", "points": points, "batched_ms": round(tb, 3),
-            "per_grid_ms": round(tp, 3), "batched_GPts": round(upd / (tb * 1e-3) / 1e9, 1),
+    return {"workload": "batch_512_grids_2d_f32_50_sweeps", "points": points, "tdepth": best,
+            "batched_ms": round(tb, 3), "per_grid_ms": round(tp, 3),
+            "batched_GPts": round(upd / (tb * 1e-3) / 1e9, 1),
             "per_grid_GPts": round(upd / (tp * 1e-3) / 1e9, 1), "speedup": round(tp / tb, 2),
-            "launches_batched": steps, "launches_per_grid": steps * len(grids)}
+            "batched_ms_by_depth": {str(k): round(v, 3) for k, v in by_depth.items()},
+            "launches_batched": -(-steps // best), "launches_per_grid": steps * len(grids)}
+
+
+def measure_copy(mib=1024, reps=10):
+    """Context for the roofline: a plain device-to-device copy (torch's copy
+    kernel) of `mib` MiB, bytes read + written over its median time."""
+    import torch
+    n_el = mib * (1 << 20) // 4
+    src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        dst.copy_(src)
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[reps // 2]
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"MiB": mib, "ms": round(ms, 4), "GBs": round(2 * mib * (1 << 20) / (ms * 1e-3) / 1e9, 1)}
+
+
+def measure_workloads(reps=3):
+    """The other sweep workloads at full size, each run with lope_iterate's
+    default (tuned) kernel and depth: GPoint-updates/s and effective HBM
+    bandwidth at 2*sizeof(T) algorithmic bytes per point-update (median of
+    reps, HIP events around the whole sweep sequence)."""
+    import numpy as np
+    import torch
+
+    import paper_1502_03504_amd as L
+    import synth
+
+    cases = [("heat2d_5pt_256^2_f64_dirichlet_100_sweeps", synth.case_heat2d),
+             ("heat3d_7pt_256^3_f64_periodic_1000_sweeps", lambda: synth.case_heat3d(n=256, dtype=np.float64)),
+             ("box9_8192^2_f32_periodic_1000_sweeps", synth.case_box9),
+             ("star25_r4_512^3_f32_dirichlet_500_sweeps", synth.case_star25)]
+    out = {}
+    s = torch.cuda.current_stream()
+    for name, make in cases:
+        case = make()
+        a = L.Grid.from_array(case.field, case.h)
+        b = a.empty_like()
+        pts, esize = int(case.field.size), case.field.dtype.itemsize
+        case = case._replace(field=None)
+        vid = L.lope_select_variant(a, case.stencil, 0)
+        info = L.lope_variant_info(vid) if vid > 0 else "generic"
+        L.lope_iterate(a, b, case.stencil, case.bc, case.steps)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            L.lope_iterate(a, b, case.stencil, case.bc, case.steps)
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[reps // 2]
+        upd = pts * case.steps / (ms * 1e-3)
+        out[name] = {"ms": round(ms, 3), "GPts": round(upd / 1e9, 1),
+                     "effective_GBs": round(upd * 2 * esize / 1e9, 1),
+                     "frac": round(upd * 2 * esize / 1e9 / PEAK_HBM_GBS, 4), "kernel": info.split()[0]}
+        log("workload:", name, out[name])
+        del a, b
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -171,6 +249,7 @@ def main():
                          "reference for hardware byte counters)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-grids measurement")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size sweep workloads")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -247,6 +326,12 @@ def main():
         torch.cuda.empty_cache()
         batch = measure_batch()
         log("batch:", batch)
+    copy_ref = measure_copy()
+    log("copy:", copy_ref)
+    workloads = None
+    if not args.no_workloads:
+        torch.cuda.empty_cache()
+        workloads = measure_workloads()
 
     cpu = None
     if args.cpu_sweeps > 0:
@@ -281,6 +366,8 @@ def main():
         "cpu_baseline": cpu,
         "adjoint_forward": adjoint,
         "batch": batch,
+        "copy_reference": copy_ref,
+        "workloads": workloads,
     }
     print(json.dumps(out), flush=True)
 

@@ -234,17 +234,20 @@ typedef struct lope_batch_plan lope_batch_plan;
 /* Build a plan for n_items grids and n_steps sweeps each: validates every
  * item, cuts every grid into tiles of the 2D marching kernel, and uploads the
  * grid and tile tables (the plan owns this device memory).  The plan borrows
- * the grids' memory until it is destroyed.  Supports 2D float32 grids up to
- * 2048 columns or float64 grids up to 1024 columns, radius <= 1 stencils, one
- * dtype per batch (else LOPE_ERR_UNSUPPORTED / LOPE_ERR_INVALID_ARG).
+ * the grids' memory until it is destroyed.  Supports 2D float32 or float64
+ * grids of any extents, radius <= 1 stencils, one dtype per batch (else
+ * LOPE_ERR_UNSUPPORTED / LOPE_ERR_INVALID_ARG).
  * `stream` is unused (creation synchronises its uploads). */
 int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_t n_steps,
                            void* stream, lope_batch_plan** out);
 
-/* Advance every grid n_steps sweeps from the state in its src: each launch
- * covers every tile of every grid and fuses tdepth sweeps (about
- * n_steps/tdepth launches in total).  lope_batch_result_index tells which
- * buffer holds the result. */
+/* Advance every grid n_steps sweeps from the state in its src: each kernel
+ * launch covers every tile of every grid and fuses tdepth sweeps (about
+ * n_steps/tdepth launches in total).  The first call for a depth records
+ * those launches into a HIP graph owned by the plan; later calls replay it on
+ * `stream` (one graph launch).  When `stream` is itself being captured, the
+ * launches are enqueued directly into the caller's graph instead.
+ * lope_batch_result_index tells which buffer holds the result. */
 int lope_batch_apply(lope_batch_plan* plan, void* stream);
 
 /* Same work as lope_batch_apply as ordinary lope_iterate launches, one per

@@ -416,12 +416,15 @@ struct lope_batch_plan {
     BatchGrid* d_grids = nullptr;
     BatchItem* d_items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // tile tables per depth
     int nitems[5] = {0, 0, 0, 0, 0};
+    hipGraphExec_t graph = nullptr;   // every pass of lope_batch_apply, recorded for graph_depth
+    int graph_depth = 0;
 };
 
 namespace {
 
 void plan_free(lope_batch_plan* p) {
     if (!p) return;
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
     if (p->d_grids) (void)hipFree(p->d_grids);
     for (int d = 0; d < 5; ++d)
         if (p->d_items[d]) (void)hipFree(p->d_items[d]);
@@ -469,6 +472,40 @@ int plan_items(lope_batch_plan* p, int depth) {
 // the remaining n mod tdepth sweeps.
 int64_t plan_passes(const lope_batch_plan* p) {
     return p->n_steps / p->tdepth + (p->n_steps % p->tdepth ? 1 : 0);
+}
+
+// Every pass of lope_batch_apply on stream s: full passes of tdepth sweeps
+// alternating src->dst and dst->src, then the remainder pass.
+hipError_t enqueue_batch_passes(const lope_batch_plan* p, hipStream_t s) {
+    const int64_t full = p->n_steps / p->tdepth;
+    const int rem = (int)(p->n_steps % p->tdepth);
+    int64_t pass = 0;
+    for (; pass < full; ++pass) {
+        const hipError_t e = launch_batch_pass(p->d_grids, p->d_items[p->tdepth], p->nitems[p->tdepth], p->tdepth,
+                                               (int)(pass & 1), p->dtype, s);
+        if (e != hipSuccess) return e;
+    }
+    if (rem) return launch_batch_pass(p->d_grids, p->d_items[rem], p->nitems[rem], rem, (int)(pass & 1), p->dtype, s);
+    return hipSuccess;
+}
+
+// Records the passes once into an executable graph (kernel nodes only) on a
+// private stream; replaying it costs one launch per lope_batch_apply.
+hipError_t record_batch_graph(const lope_batch_plan* p, hipGraphExec_t* out) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t le = enqueue_batch_passes(p, cs);
+        e = hipStreamEndCapture(cs, &g);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    return e;
 }
 
 }  // namespace
@@ -691,8 +728,6 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         if (it.src.dtype != dtype) return fail(LOPE_ERR_INVALID_ARG, "%s: all grids of a batch share one dtype", a);
         if (it.stencil.radius > 1) return fail(LOPE_ERR_UNSUPPORTED, "%s: batch stencils have radius <= 1", a);
         if (it.src.h < 1 || it.dst.h < 1) return fail(LOPE_ERR_HALO_TOO_SMALL, "%s: batch grids need h >= 1", a);
-        const int64_t maxw = dtype == LOPE_F64 ? 1024 : 2048;
-        if (it.src.n[0] > maxw) return fail(LOPE_ERR_UNSUPPORTED, "%s: rows wider than %lld", a, (long long)maxw);
         if ((rc = check_alias(&it.src, &it.dst, a, b))) return rc;
     }
     if ((rc = device_ready())) return rc;
@@ -793,20 +828,24 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream) {
     if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
     int rc;
     if ((rc = device_ready())) return rc;
-    const int64_t full = plan->n_steps / plan->tdepth;
-    const int rem = (int)(plan->n_steps % plan->tdepth);
-    int64_t pass = 0;
-    for (; pass < full; ++pass) {
-        const hipError_t e = launch_batch_pass(plan->d_grids, plan->d_items[plan->tdepth], plan->nitems[plan->tdepth],
-                                               plan->tdepth, (int)(pass & 1), plan->dtype, (hipStream_t)stream);
-        if (e != hipSuccess) return hip_fail(e, "batch pass launch");
+    if (plan_passes(plan) == 0) return LOPE_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return hip_fail(e, "stream capture query");
+    if (cap != hipStreamCaptureStatusNone) {
+        // the caller is recording a graph: its graph takes the launches
+        e = enqueue_batch_passes(plan, s);
+        return e == hipSuccess ? LOPE_OK : hip_fail(e, "batch pass launch");
     }
-    if (rem) {
-        const hipError_t e = launch_batch_pass(plan->d_grids, plan->d_items[rem], plan->nitems[rem], rem,
-                                               (int)(pass & 1), plan->dtype, (hipStream_t)stream);
-        if (e != hipSuccess) return hip_fail(e, "batch pass launch");
+    if (!plan->graph || plan->graph_depth != plan->tdepth) {
+        if (plan->graph) (void)hipGraphExecDestroy(plan->graph);
+        plan->graph = nullptr;
+        if ((e = record_batch_graph(plan, &plan->graph)) != hipSuccess) return hip_fail(e, "batch graph recording");
+        plan->graph_depth = plan->tdepth;
     }
-    return LOPE_OK;
+    e = hipGraphLaunch(plan->graph, s);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "batch graph launch");
 }
 
 int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream) {

@@ -6,9 +6,10 @@
 // (the z neighbours).  The centre plane of the tile plus its x/y halo
 // (R rows above and below, R columns left and right; the star needs no
 // corners) is published in LDS, double-buffered, one barrier per plane.
-// Core planes are fetched R+2 planes ahead of the plane being computed and
-// halos two planes ahead (two alternating prefetch buffers), so the loads of
-// the next two steps are in flight while this one computes.
+// Core planes are fetched R+1+PF planes ahead of the plane being computed
+// and halos PF planes ahead (PF = 1 or 2 alternating prefetch buffers), so
+// the loads of the next PF steps are in flight while this one computes; the
+// deeper prefetch costs registers, which the wider stencils cannot spare.
 //
 // The LDS row holds the core at a 16-byte aligned column (kLead) so the
 // centre and y-neighbour rows are read as vectors.  Every point is summed as

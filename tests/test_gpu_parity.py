@@ -287,6 +287,45 @@ def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
     plan.close()
 
 
+def test_batch_graph_replays_and_caller_capture():
+    """lope_batch_apply replays its recorded graph; replays with eager work in
+    between, and a caller's own captured graph, give the eager result."""
+    rng = np.random.default_rng([synth.CFG_TEST, 402])
+    n = 7
+    entries, fields = _batch_entries(rng, 12, np.float32, lo=3, hi=300)
+
+    def reset():
+        for (src, _, _, _), u in zip(entries, fields):
+            src.interior().copy_(torch.from_numpy(u).cuda())
+
+    plan = L.BatchPlan(entries, n)
+    plan.set_depth(3)
+    reset()
+    plan.apply_per_grid()
+    torch.cuda.synchronize()
+    ref = [plan.per_grid_result(i).numpy() for i in range(len(entries))]
+    for rep in range(3):
+        reset()
+        plan.apply()
+        torch.cuda.synchronize()
+        for i in range(len(entries)):
+            np.testing.assert_array_equal(plan.result(i).numpy(), ref[i], err_msg="replay %d grid %d" % (rep, i))
+    g = torch.cuda.CUDAGraph()
+    reset()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.apply()
+    for rep in range(3):
+        reset()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(entries)):
+            np.testing.assert_array_equal(plan.result(i).numpy(), ref[i], err_msg="captured %d grid %d" % (rep, i))
+    del g
+    plan.close()
+
+
 def test_errors_on_device():
     u = _field((8, 9, 10), np.float32, 9)
     a = grid_from(u, 1)
