@@ -250,6 +250,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-grids measurement")
     ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size sweep workloads")
+    ap.add_argument("--no-converge", action="store_true", help="skip the convergence-checked iteration")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -315,6 +316,21 @@ def main():
     alg_bytes_per_launch = 8.0 * pts * td
     achieved = alg_bytes_per_launch / launch_s / 1e9
 
+    converge = None
+    if not args.no_converge:
+        converge = {}
+        scratch = torch.empty(1, dtype=torch.float64, device="cuda")
+        for every in (10, 100):
+            # tol < 0: never converged, so every run does all sweeps and all checks
+            L.lope_iterate_until(a, b, st, bc, every, every, -1.0, scratch=scratch)
+            t = time.perf_counter()
+            _, done, _ = L.lope_iterate_until(a, b, st, bc, sweeps, every, -1.0, scratch=scratch)
+            el = time.perf_counter() - t
+            converge["check_every_%d" % every] = {"sweeps": done, "ms": round(el * 1e3, 2),
+                                                  "GPts": round(pts * done / el / 1e9, 1),
+                                                  "vs_plain": round(pts * done / el / 1e9 / value, 3)}
+        log("converge:", converge)
+
     adjoint = None
     if not args.no_adjoint:
         del a, b
@@ -364,6 +380,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(info.split()[0], n, sweeps)},
         "cpu_baseline": cpu,
+        "converge": converge,
         "adjoint_forward": adjoint,
         "batch": batch,
         "copy_reference": copy_ref,

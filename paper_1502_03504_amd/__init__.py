@@ -22,7 +22,7 @@ from ._lib import LopeError, check, load
 
 __all__ = [
     "Grid", "LopeError", "lope_get_device", "lope_halo_fill", "lope_apply", "lope_iterate",
-    "lope_iterate_tuned", "lope_apply_adjoint", "lope_apply_var", "lope_apply_var_adjoint",
+    "lope_iterate_tuned", "lope_iterate_until", "lope_apply_adjoint", "lope_apply_var", "lope_apply_var_adjoint",
     "lope_accumulate", "lope_variant_count", "lope_variant_info", "lope_select_variant",
     "lope_tune_set", "variants", "BatchPlan", "lope_batch_plan_create", "lope_batch_apply",
     "lope_batch_apply_per_grid", "lope_batch_plan_destroy", "DIRICHLET", "PERIODIC",
@@ -247,6 +247,27 @@ def lope_iterate_tuned(a: Grid, b: Grid, stencil, bc, n_steps: int, variant: int
     check(load().lope_iterate_tuned(_ref(ga), _ref(gb), _ref(s.c), _ref(_bc(bc, a.ndim)), int(n_steps), _ref(t),
                                     _stream(stream), _ref(idx)))
     return idx.value
+
+
+def lope_iterate_until(a: Grid, b: Grid, stencil, bc, max_steps: int, check_every: int, tol: float,
+                       tdepth: int = 0, scratch: torch.Tensor = None, stream=None):
+    """Sweeps until the max-norm change of a checked sweep is <= tol (checked
+    every ``check_every`` sweeps) or ``max_steps`` sweeps ran.  Waits on the
+    stream after each check.  Returns (result_index, steps_done, residual);
+    ``scratch`` is an optional float64 device tensor of >= 1 element."""
+    st = _Stencil(stencil)
+    ga, gb = a.descriptor(), b.descriptor()
+    if scratch is None:
+        scratch = torch.empty(1, dtype=torch.float64, device=a.storage.device)
+    if scratch.dtype != torch.float64 or scratch.numel() < 1 or not scratch.is_cuda:
+        raise TypeError("scratch must be a float64 device tensor")
+    steps = ctypes.c_int64(-1)
+    res = ctypes.c_double(0.0)
+    idx = ctypes.c_int32(-1)
+    check(load().lope_iterate_until(_ref(ga), _ref(gb), _ref(st.c), _ref(_bc(bc, a.ndim)), int(max_steps),
+                                    int(check_every), float(tol), int(tdepth), ctypes.c_void_p(scratch.data_ptr()),
+                                    _stream(stream), _ref(steps), _ref(res), _ref(idx)))
+    return idx.value, steps.value, res.value
 
 
 def lope_apply_adjoint(ybar: Grid, xbar: Grid, stencil, bc, gbar: torch.Tensor = None, stream=None) -> None:

@@ -87,6 +87,10 @@ SIGNATURES = {
                                     ctypes.c_int32, c_void_p, P(ctypes.c_int32)]),
     "lope_iterate_tuned": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stencil), P(lope_bc),
                                           ctypes.c_int64, P(lope_tuning), c_void_p, P(ctypes.c_int32)]),
+    "lope_iterate_until": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stencil), P(lope_bc),
+                                          ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                          c_void_p, c_void_p, P(ctypes.c_int64), P(ctypes.c_double),
+                                          P(ctypes.c_int32)]),
     "lope_apply_adjoint": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stencil), P(lope_bc),
                                           c_void_p, c_void_p]),
     "lope_apply_var": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_varcoef), P(lope_bc), c_void_p]),

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <string>
@@ -160,6 +161,28 @@ int check_memory(const lope_grid* g, const char* name) {
     return LOPE_OK;
 }
 
+// `bytes` bytes at p lie in one device allocation of the current device.
+int check_device_pointer(const void* p, size_t bytes, const char* name) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess || (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+        (void)hipGetLastError();
+        return fail(LOPE_ERR_INVALID_ARG, "%s must be a device pointer", name);
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) == hipSuccess && attr.device != dev)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: memory is on device %d, current device is %d", name, attr.device, dev);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if ((e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LOPE_ERR_INVALID_ARG, "%s: cannot query allocation range (%s)", name, hipGetErrorString(e));
+    }
+    if ((uintptr_t)p + bytes > (uintptr_t)base + size)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: %zu bytes do not fit its allocation", name, bytes);
+    return LOPE_OK;
+}
+
 DevGrid dev_grid(const lope_grid* g) {
     DevGrid d;
     d.origin = g->origin;
@@ -230,6 +253,8 @@ struct Registry {
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = star3d_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
+        n = star3d_flat_variants(&p);
+        for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = plane2d_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
     }
@@ -256,6 +281,8 @@ TuneKey tune_key(int ndim, int radius, int dtype, bool star, int64_t points, int
 bool variant_fits(const Variant& v, const SweepJob& j, int tdepth) {
     if (v.ndim != j.ndim || v.radius != j.radius || v.dtype != j.dtype || v.tdepth != tdepth) return false;
     if (v.family == FAM_STAR3D) return j.star;
+    if (v.family == FAM_STAR3D_FLAT)   // 32-bit in-plane offsets
+        return j.star && j.src.sz < ((int64_t)1 << 31) && j.dst.sz < ((int64_t)1 << 31);
     if (v.family == FAM_PLANE2D) return v.box ? true : j.star;
     if (v.family == FAM_STAR3D_VEC) {
         // 16-byte vectors: aligned origins, strides in whole vectors
@@ -548,6 +575,68 @@ int lope_iterate(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
     return iterate_impl(a, b, st, bc, n_steps, tdepth, 0, 0, stream, result_index);
 }
 
+int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stencil* st, const lope_bc* bc,
+                       int64_t max_steps, int32_t check_every, double tol, int32_t tdepth, double* residual_scratch,
+                       void* stream, int64_t* steps_done, double* residual, int32_t* result_index) {
+    if (!steps_done || !residual || !result_index) return fail(LOPE_ERR_INVALID_ARG, "null output pointer");
+    *steps_done = 0;
+    *residual = std::nan("");
+    *result_index = 0;
+    if (check_every < 1) return fail(LOPE_ERR_INVALID_ARG, "check_every %d < 1", check_every);
+    if (max_steps < 0) return fail(LOPE_ERR_INVALID_ARG, "max_steps %lld < 0", (long long)max_steps);
+    if (!residual_scratch || ((uintptr_t)residual_scratch & 7))
+        return fail(LOPE_ERR_INVALID_ARG, "residual_scratch must be an 8-byte aligned device pointer");
+    int rc;
+    int32_t idx = 0;
+    // full validation of the grids, stencil and rule (zero sweeps launch nothing)
+    if ((rc = iterate_impl(a, b, st, bc, 0, tdepth, 0, 0, stream, &idx))) return rc;
+    if ((rc = check_device_pointer(residual_scratch, sizeof(double), "residual_scratch"))) return rc;
+    if (is_empty(a)) return LOPE_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return hip_fail(e, "stream capture query");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(LOPE_ERR_UNSUPPORTED, "lope_iterate_until waits on the host; it cannot be captured");
+    const DevGrid ga = dev_grid(a), gb = dev_grid(b);
+    int cur = 0;   // buffer holding the state: 0 = a, 1 = b
+    int64_t done = 0;
+    while (done < max_steps) {
+        const int64_t to_check = check_every - done % check_every;
+        const int64_t left = max_steps - done;
+        if (to_check > left) {   // no check within the budget: plain sweeps
+            if ((rc = iterate_impl(cur ? b : a, cur ? a : b, st, bc, left, tdepth, 0, 0, stream, &idx))) return rc;
+            cur ^= idx;
+            done = max_steps;
+            break;
+        }
+        if (to_check > 1) {
+            if ((rc = iterate_impl(cur ? b : a, cur ? a : b, st, bc, to_check - 1, tdepth, 0, 0, stream, &idx)))
+                return rc;
+            cur ^= idx;
+        }
+        // the checked sweep alone, then the residual between the two buffers
+        if ((rc = iterate_impl(cur ? b : a, cur ? a : b, st, bc, 1, 1, 0, 0, stream, &idx))) return rc;
+        const DevGrid& prev = cur ? gb : ga;
+        const DevGrid& next = cur ? ga : gb;
+        cur ^= 1;
+        done += to_check;
+        if ((e = launch_residual_max(prev, next, a->dtype, residual_scratch, s)) != hipSuccess)
+            return hip_fail(e, "residual launch");
+        double r = 0.0;
+        if ((e = hipMemcpyAsync(&r, residual_scratch, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(e, "residual read-back");
+        *residual = r;
+        *steps_done = done;
+        *result_index = cur;
+        if (r <= tol) return LOPE_OK;
+    }
+    *steps_done = done;
+    *result_index = cur;
+    return LOPE_OK;
+}
+
 int lope_iterate_tuned(const lope_grid* a, const lope_grid* b, const lope_stencil* st, const lope_bc* bc,
                        int64_t n_steps, const lope_tuning* tune, void* stream, int32_t* result_index) {
     if (!tune) return fail(LOPE_ERR_INVALID_ARG, "null tuning");
@@ -567,14 +656,7 @@ int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_
     if ((rc = check_alias(ybar, xbar, "ybar", "xbar"))) return rc;
     if ((rc = device_ready())) return rc;
     if ((rc = check_memory(ybar, "ybar")) || (rc = check_memory(xbar, "xbar"))) return rc;
-    if (gbar_dirichlet) {
-        hipPointerAttribute_t attr;
-        if (hipPointerGetAttributes(&attr, gbar_dirichlet) != hipSuccess ||
-            (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
-            (void)hipGetLastError();
-            return fail(LOPE_ERR_INVALID_ARG, "gbar_dirichlet must be a device pointer");
-        }
-    }
+    if (gbar_dirichlet && (rc = check_device_pointer(gbar_dirichlet, sizeof(double), "gbar_dirichlet"))) return rc;
     const hipStream_t s = (hipStream_t)stream;
     static thread_local SweepJob job;
     if (is_empty(ybar)) {

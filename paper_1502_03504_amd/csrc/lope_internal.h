@@ -55,9 +55,11 @@ hipError_t launch_halo_fill(const DevGrid& g, int ndim, int h, int dtype, const 
 hipError_t launch_accumulate(const DevGrid& part, int part_dtype, const DevGrid& total,
                              hipStream_t s);
 hipError_t launch_gbar(const SweepJob& j, double* out, hipStream_t s);
+// *out (device) = max over the interior of |y - x| in float64 (x, y same extents)
+hipError_t launch_residual_max(const DevGrid& x, const DevGrid& y, int dtype, double* out, hipStream_t s);
 
 // Tuned kernel families.
-enum Family { FAM_GENERIC = 0, FAM_STAR3D = 1, FAM_PLANE2D = 2, FAM_STAR3D_VEC = 3 };
+enum Family { FAM_GENERIC = 0, FAM_STAR3D = 1, FAM_PLANE2D = 2, FAM_STAR3D_VEC = 3, FAM_STAR3D_FLAT = 4 };
 
 typedef hipError_t (*VariantFn)(const SweepJob& j, int chunk, hipStream_t s);
 
@@ -73,6 +75,7 @@ struct Variant {
 
 // Registries filled by each kernel file.
 int star3d_variants(const Variant** out);
+int star3d_flat_variants(const Variant** out);
 int star3d_vec_variants(const Variant** out);
 int star3d_vtb_variants(const Variant** out);
 int plane2d_variants(const Variant** out);

@@ -1,6 +1,7 @@
 """The C ABI without a GPU: the library loads, exports every declared symbol,
 and structural validation returns the documented codes before any HIP call."""
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -138,6 +139,27 @@ def test_invalid_arguments():
                           ctypes.byref(bc()), 1, 9, None, ctypes.byref(idx)) == E
     assert L.lope_iterate(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), ctypes.byref(s),
                           ctypes.byref(bc()), 1, 0, None, None) == E
+
+
+def test_iterate_until_validation():
+    s, _keep = stencil()
+    E = _lib.LOPE_ERR_INVALID_ARG
+    steps, res, idx = ctypes.c_int64(9), ctypes.c_double(0), ctypes.c_int32(9)
+    outs = (ctypes.byref(steps), ctypes.byref(res), ctypes.byref(idx))
+
+    def call(max_steps=10, every=2, scratch=0x200000, tdepth=0, a=None, o=outs):
+        return L.lope_iterate_until(ctypes.byref(a or grid()), ctypes.byref(grid(origin=far())), ctypes.byref(s),
+                                    ctypes.byref(bc()), max_steps, every, 1e-6, tdepth, scratch, None, *o)
+
+    assert call(every=0) == E
+    assert steps.value == 0 and idx.value == 0 and math.isnan(res.value)
+    assert call(max_steps=-1) == E
+    assert call(scratch=None) == E
+    assert call(scratch=0x200004) == E                     # not 8-byte aligned
+    assert call(o=(None, ctypes.byref(res), ctypes.byref(idx))) == E
+    assert call(tdepth=7) == E
+    assert call(a=grid(sy=5)) == E
+    assert call() == _lib.LOPE_ERR_NO_DEVICE                  # valid, but no GPU here
 
 
 def test_halo_too_small():
