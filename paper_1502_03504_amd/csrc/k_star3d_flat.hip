@@ -233,13 +233,23 @@ hipError_t run_star3d_flat(const SweepJob& j, int chunk, hipStream_t s) {
      BX, BY, NT, CH, &run_star3d_flat<T, R, TD, BX, BY, NT>}
 
 const Variant kStar3dFlat[] = {
-    FSTAR(float, LOPE_F32, 1, 2, 64, 32, 512, 64),
     FSTAR(float, LOPE_F32, 1, 3, 64, 32, 512, 128),
+    FSTAR(float, LOPE_F32, 1, 3, 64, 32, 768, 128),
+    FSTAR(float, LOPE_F32, 1, 3, 64, 32, 1024, 128),
+    FSTAR(float, LOPE_F32, 1, 3, 128, 16, 512, 128),
     FSTAR(float, LOPE_F32, 1, 3, 64, 16, 256, 128),
-    FSTAR(float, LOPE_F32, 1, 4, 64, 32, 512, 128),
-    FSTAR(float, LOPE_F32, 1, 4, 64, 16, 256, 128),
-    FSTAR(double, LOPE_F64, 1, 2, 32, 32, 256, 64),
-    FSTAR(double, LOPE_F64, 1, 3, 32, 32, 256, 64),
+    FSTAR(float, LOPE_F32, 1, 2, 64, 32, 512, 128),
+    FSTAR(float, LOPE_F32, 1, 2, 64, 32, 1024, 128),
+    FSTAR(float, LOPE_F32, 1, 4, 64, 32, 512, 256),
+    FSTAR(float, LOPE_F32, 1, 4, 64, 32, 1024, 256),
+    FSTAR(float, LOPE_F32, 1, 4, 64, 16, 256, 256),
+    FSTAR(float, LOPE_F32, 4, 1, 64, 32, 512, 128),
+    FSTAR(float, LOPE_F32, 4, 2, 64, 32, 1024, 128),
+    FSTAR(double, LOPE_F64, 1, 3, 32, 32, 256, 32),
+    FSTAR(double, LOPE_F64, 1, 3, 32, 32, 512, 32),
+    FSTAR(double, LOPE_F64, 1, 3, 64, 16, 512, 32),
+    FSTAR(double, LOPE_F64, 1, 2, 32, 32, 256, 32),
+    FSTAR(double, LOPE_F64, 1, 4, 32, 32, 512, 32),
 };
 
 }  // namespace
