@@ -257,6 +257,8 @@ struct Registry {
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = plane2d_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
+        n = plane2d_wave_variants(&p);
+        for (int i = 0; i < n; ++i) v.push_back(p[i]);
     }
 };
 Registry& registry() {
@@ -281,8 +283,10 @@ TuneKey tune_key(int ndim, int radius, int dtype, bool star, int64_t points, int
 bool variant_fits(const Variant& v, const SweepJob& j, int tdepth) {
     if (v.ndim != j.ndim || v.radius != j.radius || v.dtype != j.dtype || v.tdepth != tdepth) return false;
     if (v.family == FAM_STAR3D) return j.star;
-    if (v.family == FAM_STAR3D_FLAT)   // 32-bit in-plane offsets
-        return j.star && j.src.sz < ((int64_t)1 << 31) && j.dst.sz < ((int64_t)1 << 31);
+    if (v.family == FAM_STAR3D_FLAT) {   // in-plane byte offsets within 31 bits
+        const int64_t esize = j.dtype == LOPE_F64 ? 8 : 4;
+        return j.star && j.src.sz * esize < ((int64_t)1 << 31) && j.dst.sz * esize < ((int64_t)1 << 31);
+    }
     if (v.family == FAM_PLANE2D) return v.box ? true : j.star;
     if (v.family == FAM_STAR3D_VEC) {
         // 16-byte vectors: aligned origins, strides in whole vectors
@@ -419,7 +423,7 @@ int iterate_impl(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
 
 
 // ---- batch plans ----
-constexpr int kBatchRows = 64;        // rows per batch tile
+constexpr int kBatchRows = 128;       // rows per batch strip
 constexpr int kBatchDefaultDepth = 2; // sweeps per pass unless set
 
 struct PlanGrid {
@@ -458,18 +462,17 @@ void plan_free(lope_batch_plan* p) {
     delete p;
 }
 
-// Tile table for passes of `depth` sweeps: per grid (in plan order), tiles of
-// the narrow width if the whole row fits one, else of the wide width, by
-// chunks of kBatchRows rows.  Built and uploaded once per depth.
+// Work table for passes of `depth` sweeps: per grid (in plan order), strips
+// of batch_strip_width(depth) output columns by chunks of kBatchRows rows,
+// one entry per wave.  Built and uploaded once per depth.
 int plan_items(lope_batch_plan* p, int depth) {
     if (p->d_items[depth]) return LOPE_OK;
     std::vector<BatchItem> items;
+    const int64_t bw = batch_strip_width(depth);
     for (int64_t gi : p->order) {
         const lope_grid& g = p->grids[(size_t)gi].src;
         const int64_t nx = g.n[0], ny = g.n[1];
         if (nx == 0 || ny == 0) continue;
-        const bool wide = nx > batch_tile_width(depth, false);
-        const int64_t bw = batch_tile_width(depth, wide);
         for (int64_t y0 = 0; y0 < ny; y0 += kBatchRows)
             for (int64_t x0 = 0; x0 < nx; x0 += bw) {
                 BatchItem it{};
@@ -477,7 +480,6 @@ int plan_items(lope_batch_plan* p, int depth) {
                 it.x0 = (int32_t)x0;
                 it.y0 = (int32_t)y0;
                 it.y1 = (int32_t)std::min(ny, y0 + kBatchRows);
-                it.wide = wide ? 1 : 0;
                 items.push_back(it);
             }
     }

@@ -1,81 +1,89 @@
-// Batched sweeps: many independent 2D grids (radius-1 star or box
-// stencils, each with its own boundary rule), advanced together.
+// Batched sweeps: many independent 2D grids (radius-1 star or box stencils,
+// each with its own coefficients and boundary rule), advanced together.
 //
-// The plan cuts every grid into tiles of the 2D marching kernel (BX output
-// columns by a chunk of rows; a narrow 256-wide tile for grids that fit one,
-// else 512-wide tiles) and lists them in a work table.  One launch sweeps
-// every tile of every grid TD times (temporal blocking, plane2d_tile), so a
-// batch of G grids advances n sweeps in about n/TD launches instead of G*n.
-// Tiles of one launch are independent: each reads the state before the pass
-// and writes only its own output cells of the other buffer.  Work-table
-// entries of one grid are consecutive, and workgroup ids are laid out so that
-// consecutive entries run on one XCD (workgroup b runs on XCD b mod 8),
-// keeping a grid's shared boundary rows in one L2.  Per point the result
-// equals lope_iterate's, value for value.
-#include "plane2d_tile.h"
+// The plan cuts every grid into strips of 64 - 2*TD output columns by chunks
+// of rows and lists them in a work table, one entry per wavefront.  One
+// launch sweeps every strip of every grid TD times (plane2d_wave_strip: a
+// wave marches its strip with the x neighbours moved across lanes and the
+// rows in registers), so a batch of G grids advances n sweeps in about n/TD
+// launches instead of G*n.  Entries of one launch are independent: each reads
+// the state before the pass and writes only its own output cells of the other
+// buffer.  Entries of one grid are consecutive, and workgroup ids are laid
+// out so that consecutive entries run on one XCD (workgroup b runs on XCD
+// b mod 8), keeping a grid's shared halo rows and columns in one L2.  Per
+// point the result equals lope_iterate's, value for value.
+#include "plane2d_wave.h"
 
 namespace lope {
 namespace {
 
-constexpr int kBatchThreads = 256;
+constexpr int kBatchWaves = 4;   // waves per workgroup
 
-template <typename T, int TD>
-__global__ void __launch_bounds__(kBatchThreads)
-k_batch_td(const BatchGrid* __restrict__ grids, const BatchItem* __restrict__ items, int nitems, int nitems_padded,
-           int parity) {
-    constexpr int NT = kBatchThreads;
-    constexpr int BXW = 2 * NT - 2 * TD;   // wide tile: 512 columns with halo
-    constexpr int BXN = NT - 2 * TD;       // narrow tile: 256 columns with halo
-    __shared__ T lds[Plane2dShape<T, 1, TD, BXW, NT>::LDS_ELEMS];
-    const int logical = xcd_logical_block(nitems_padded);
-    if (logical >= nitems) return;
-    const BatchItem it = items[logical];
-    const BatchGrid& gr = grids[it.grid];
-    const DevGrid in = parity ? gr.dst : gr.src;
-    const DevGrid out = parity ? gr.src : gr.dst;
-    T cf[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) cf[t] = (T)gr.c[t];
-    if (it.wide) {
-        if (gr.box)
-            plane2d_tile<T, 1, TD, BXW, NT, true>(in, out, gr.rule, cf, it.x0, it.y0, it.y1, lds);
-        else
-            plane2d_tile<T, 1, TD, BXW, NT, false>(in, out, gr.rule, cf, it.x0, it.y0, it.y1, lds);
-    } else {
-        if (gr.box)
-            plane2d_tile<T, 1, TD, BXN, NT, true>(in, out, gr.rule, cf, it.x0, it.y0, it.y1, lds);
-        else
-            plane2d_tile<T, 1, TD, BXN, NT, false>(in, out, gr.rule, cf, it.x0, it.y0, it.y1, lds);
-    }
+template <typename T, int TD, bool BOX>
+__device__ __forceinline__ void batch_strip(const BatchGrid& gr, const DevGrid& in, const DevGrid& out,
+                                            const T (&c9)[9], const BatchItem& it) {
+    const T g = (T)gr.rule.g;
+    const bool dx = gr.rule.per[0] == 0, dy = gr.rule.per[1] == 0;
+    if (dx && dy)
+        plane2d_wave_strip<T, TD, BOX, true, true>(in, out, g, c9, it.x0, it.y0, it.y1);
+    else if (dx)
+        plane2d_wave_strip<T, TD, BOX, true, false>(in, out, g, c9, it.x0, it.y0, it.y1);
+    else if (dy)
+        plane2d_wave_strip<T, TD, BOX, false, true>(in, out, g, c9, it.x0, it.y0, it.y1);
+    else
+        plane2d_wave_strip<T, TD, BOX, false, false>(in, out, g, c9, it.x0, it.y0, it.y1);
 }
 
 template <typename T, int TD>
-void launch_td(const BatchGrid* grids, const BatchItem* items, int nitems, int nbp, int parity, hipStream_t s) {
-    hipLaunchKernelGGL((k_batch_td<T, TD>), dim3(nbp), dim3(kBatchThreads), 0, s, grids, items, nitems, nbp, parity);
+__global__ void __launch_bounds__(kBatchWaves * 64)
+k_batch_wave(const BatchGrid* __restrict__ grids, const BatchItem* __restrict__ items, int nitems,
+             int nblocks_padded, int parity) {
+    // one work-table entry per wave; the index is uniform across the wave
+    const int w = xcd_logical_block(nblocks_padded) * kBatchWaves +
+                  __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (w >= nitems) return;   // whole waves leave; the kernel has no barrier
+    const BatchItem it = items[w];
+    const BatchGrid& gr = grids[it.grid];
+    const DevGrid in = parity ? gr.dst : gr.src;
+    const DevGrid out = parity ? gr.src : gr.dst;
+    T c9[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) c9[t] = (T)gr.c[t];
+    if (gr.box)
+        batch_strip<T, TD, true>(gr, in, out, c9, it);
+    else
+        batch_strip<T, TD, false>(gr, in, out, c9, it);
+}
+
+template <typename T, int TD>
+void launch_td(const BatchGrid* grids, const BatchItem* items, int nitems, int parity, hipStream_t s) {
+    const int nb = (nitems + kBatchWaves - 1) / kBatchWaves;
+    const int nbp = padded_block_count(nb);
+    hipLaunchKernelGGL((k_batch_wave<T, TD>), dim3(nbp), dim3(kBatchWaves * 64), 0, s, grids, items, nitems, nbp,
+                       parity);
 }
 
 }  // namespace
 
-int batch_tile_width(int tdepth, bool wide) { return (wide ? 2 * kBatchThreads : kBatchThreads) - 2 * tdepth; }
+int batch_strip_width(int tdepth) { return 64 - 2 * tdepth; }
 
 hipError_t launch_batch_pass(const BatchGrid* grids, const BatchItem* items, int nitems, int tdepth, int parity,
                              int dtype, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    const int nbp = padded_block_count(nitems);
     if (dtype == LOPE_F32) {
         switch (tdepth) {
-            case 1: launch_td<float, 1>(grids, items, nitems, nbp, parity, s); break;
-            case 2: launch_td<float, 2>(grids, items, nitems, nbp, parity, s); break;
-            case 3: launch_td<float, 3>(grids, items, nitems, nbp, parity, s); break;
-            case 4: launch_td<float, 4>(grids, items, nitems, nbp, parity, s); break;
+            case 1: launch_td<float, 1>(grids, items, nitems, parity, s); break;
+            case 2: launch_td<float, 2>(grids, items, nitems, parity, s); break;
+            case 3: launch_td<float, 3>(grids, items, nitems, parity, s); break;
+            case 4: launch_td<float, 4>(grids, items, nitems, parity, s); break;
             default: return hipErrorInvalidValue;
         }
     } else {
         switch (tdepth) {
-            case 1: launch_td<double, 1>(grids, items, nitems, nbp, parity, s); break;
-            case 2: launch_td<double, 2>(grids, items, nitems, nbp, parity, s); break;
-            case 3: launch_td<double, 3>(grids, items, nitems, nbp, parity, s); break;
-            case 4: launch_td<double, 4>(grids, items, nitems, nbp, parity, s); break;
+            case 1: launch_td<double, 1>(grids, items, nitems, parity, s); break;
+            case 2: launch_td<double, 2>(grids, items, nitems, parity, s); break;
+            case 3: launch_td<double, 3>(grids, items, nitems, parity, s); break;
+            case 4: launch_td<double, 4>(grids, items, nitems, parity, s); break;
             default: return hipErrorInvalidValue;
         }
     }

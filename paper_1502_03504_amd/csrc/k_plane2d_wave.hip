@@ -1,0 +1,82 @@
+// 2D radius-1 stencils (box or star), TD sweeps per pass, one wavefront per
+// strip of 64 - 2*TD output columns and a chunk of rows (plane2d_wave_strip):
+// no LDS and no barriers.  Workgroups of NW waves; consecutive waves take
+// neighbouring strips of the same rows.
+#include "plane2d_wave.h"
+
+namespace lope {
+namespace {
+
+template <typename T, int TD, bool BOX, int NW, bool DX, bool DY>
+__global__ void __launch_bounds__(NW * 64)
+k_plane2d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef9<T> cf, int chunk, int strips, int nwaves,
+               int nblocks_padded) {
+    // the wave index is uniform across the wave: say so, so that rows, loop
+    // bounds and the row rule stay scalar
+    const int wave = xcd_logical_block(nblocks_padded) * NW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wave >= nwaves) return;   // whole waves leave; the kernel has no barrier
+    const int tx = wave % strips, ty = wave / strips;
+    const int y0 = ty * chunk;
+    plane2d_wave_strip<T, TD, BOX, DX, DY>(src, dst, (T)rule.g, cf.c, tx * (64 - 2 * TD), y0,
+                                           min(y0 + chunk, src.ny));
+}
+
+template <typename T, int TD, bool BOX, int NW>
+hipError_t run_plane2d_wave(const SweepJob& j, int chunk, hipStream_t s) {
+    Coef9<T> cf;
+    for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+            cf.c[(ox + 1) + 3 * (oy + 1)] = (T)j.dense[(ox + 1) + (oy + 1) * 3];
+        }
+    if (chunk <= 0) chunk = 128;
+    const int out_cols = 64 - 2 * TD;
+    const int strips = (j.src.nx + out_cols - 1) / out_cols;
+    const int chunks = (j.src.ny + chunk - 1) / chunk;
+    const int64_t nw64 = (int64_t)strips * chunks;
+    if (nw64 > (1ll << 30)) return hipErrorInvalidConfiguration;
+    const int nw = (int)nw64;
+    const int nb = (nw + NW - 1) / NW;
+    const int nbp = padded_block_count(nb);
+    const bool dx = !j.rule.per[0], dy = !j.rule.per[1];
+#define LOPE_WAVE_LAUNCH(A, B)                                                                                 \
+    hipLaunchKernelGGL((k_plane2d_wave<T, TD, BOX, NW, A, B>), dim3(nbp), dim3(NW * 64), 0, s, j.src, j.dst, \
+                       j.rule, cf, chunk, strips, nw, nbp)
+    if (dx && dy)
+        LOPE_WAVE_LAUNCH(true, true);
+    else if (dx)
+        LOPE_WAVE_LAUNCH(true, false);
+    else if (dy)
+        LOPE_WAVE_LAUNCH(false, true);
+    else
+        LOPE_WAVE_LAUNCH(false, false);
+#undef LOPE_WAVE_LAUNCH
+    return hipGetLastError();
+}
+
+#define PWAVE(T, DT, TD, BOX, NW, CH)                                                                  \
+    {"plane2dw_" #T "_r1_t" #TD "_nw" #NW "_" #BOX, FAM_PLANE2D, 2, 1, TD, DT, BOX, 64 - 2 * (TD), 0, \
+     (NW) * 64, CH, &run_plane2d_wave<T, TD, BOX, NW>}
+
+const Variant kPlane2dWave[] = {
+    PWAVE(float, LOPE_F32, 1, true, 4, 128),
+    PWAVE(float, LOPE_F32, 2, true, 4, 128),
+    PWAVE(float, LOPE_F32, 3, true, 4, 128),
+    PWAVE(float, LOPE_F32, 4, true, 4, 128),
+    PWAVE(float, LOPE_F32, 1, false, 4, 128),
+    PWAVE(float, LOPE_F32, 2, false, 4, 128),
+    PWAVE(float, LOPE_F32, 3, false, 4, 128),
+    PWAVE(float, LOPE_F32, 4, false, 4, 128),
+    PWAVE(double, LOPE_F64, 1, false, 4, 32),
+    PWAVE(double, LOPE_F64, 2, false, 4, 32),
+    PWAVE(double, LOPE_F64, 4, false, 4, 32),
+    PWAVE(double, LOPE_F64, 2, true, 4, 32),
+};
+
+}  // namespace
+
+int plane2d_wave_variants(const Variant** out) {
+    *out = kPlane2dWave;
+    return (int)(sizeof(kPlane2dWave) / sizeof(kPlane2dWave[0]));
+}
+
+}  // namespace lope

@@ -11,10 +11,14 @@
 //   every position is in bounds; the boundary rule is a select;
 // * the z loop is unrolled by the ring length 2R+1, so the ring slot holding
 //   plane z-R+s is a compile-time register at every step (no rotation);
+// * the launch bounds ask for the occupancy the LDS allows (two workgroups
+//   per CU), which keeps the register allocation within that budget;
 // * levels are computed from the deepest down, so each level's ring is
 //   updated in place right after its last reader (the level above) ran;
 // * global addresses are a per-plane base (wave-uniform) plus a 32-bit
-//   in-plane offset (the caller checks that planes fit 32-bit offsets).
+//   in-plane byte offset (the caller checks that planes fit 31 bits);
+// * on grids periodic in x and y no position holds g, and the blend is
+//   compiled out (DXY = false).
 //
 // The per-point sum is c0*v0 followed by fmas in lexicographic offset order
 // (z-R .. z-1, y-R .. y-1, x-R .. x+R, y+1 .. y+R, z+1 .. z+R), as in every
@@ -41,6 +45,12 @@ struct FlatShape {
     static constexpr int RING = 2 * R + 1;
     static constexpr int GUARD = R * W;                 // R rows before and after the tile
     static constexpr int PLANE = 2 * GUARD + NP * NT;   // one slot per (thread, position)
+    // Workgroups per CU that the LDS (160 KiB) admits, at most 2, and the
+    // waves per SIMD that this takes: the register budget the compiler must
+    // meet so that LDS, not registers, sets the occupancy.
+    static constexpr int LDS_BYTES = TD * 2 * PLANE * (int)sizeof(T);
+    static constexpr int WG_PER_CU = (160 * 1024 / LDS_BYTES) >= 2 ? 2 : 1;
+    static constexpr int WAVES_PER_EU = (WG_PER_CU * NT / 64 + 3) / 4;
 };
 
 // m ? v : g per lane as a bit blend (one VALU op per 32 bits): a select here
@@ -62,17 +72,19 @@ struct MaskOf<double> {
     typedef unsigned long long type;
 };
 
-// f(j + P, phase P) for P = 0 .. N-1, each with a compile-time phase.
+// f(j + P, phase P) for P = 0 .. N-1 while j + P <= jend, each with a
+// compile-time phase (the bound is wave-uniform).
 template <int P, int N, typename F>
-__device__ __forceinline__ void unroll_steps(int j, F& f) {
+__device__ __forceinline__ void unroll_steps(int j, int jend, F& f) {
     if constexpr (P < N) {
+        if (j + P > jend) return;
         f(j + P, std::integral_constant<int, P>{});
-        unroll_steps<P + 1, N>(j, f);
+        unroll_steps<P + 1, N>(j, jend, f);
     }
 }
 
-template <typename T, int R, int TD, int BX, int BY, int NT>
-__global__ void __launch_bounds__(NT)
+template <typename T, int R, int TD, int BX, int BY, int NT, bool DXY>
+__global__ void __launch_bounds__(NT, (FlatShape<T, R, TD, BX, BY, NT>::WAVES_PER_EU))
 k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chunk, int tiles_x, int tiles_y,
               int nblocks, int nblocks_padded) {
     typedef FlatShape<T, R, TD, BX, BY, NT> S;
@@ -91,14 +103,17 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
     const int nx = src.nx, ny = src.ny, nz = src.nz;
     const int x0 = tx * BX, y0 = ty * BY, z0 = tz * chunk;
     const int zend = min(z0 + chunk, nz);
+    // z stays a run-time rule: its wave-uniform plane checks also keep the
+    // scheduler from interleaving levels, which holds the register count down
     const bool perx = rule.per[0] != 0, pery = rule.per[1] != 0, perz = rule.per[2] != 0;
     const T g = (T)rule.g;
     const int tid = threadIdx.x;
 
     typedef typename MaskOf<T>::type M;
-    unsigned soff[NP];   // in-plane offset of the (wrapped or clamped) source column
-    unsigned doff[NP];   // in-plane offset of the output column
-    M live[NP];          // all ones, or 0 where the position holds g (outside along a Dirichlet x/y axis)
+    unsigned soff[NP];   // in-plane byte offset of the (wrapped or clamped) source column
+    unsigned doff[NP];   // in-plane byte offset of the output column
+    M live[NP];          // all ones, or 0 where the position holds g (outside along a Dirichlet x/y axis);
+                         // used only when DXY (some x or y axis is Dirichlet)
     bool keep[NP];       // an output position inside the interior
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -111,9 +126,9 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
         live[i] = ((!perx && ox) || (!pery && oy)) ? (M)0 : ~(M)0;
         const int wx = perx ? wrap_index(gx, nx) : min(max(gx, 0), nx - 1);
         const int wy = pery ? wrap_index(gy, ny) : min(max(gy, 0), ny - 1);
-        soff[i] = used ? (unsigned)wx + (unsigned)wy * (unsigned)src.sy : 0u;
+        soff[i] = used ? ((unsigned)wx + (unsigned)wy * (unsigned)src.sy) * (unsigned)sizeof(T) : 0u;
         keep[i] = used && l >= TD && !ox && !oy;
-        doff[i] = keep[i] ? (unsigned)gx + (unsigned)gy * (unsigned)dst.sy : 0u;
+        doff[i] = keep[i] ? ((unsigned)gx + (unsigned)gy * (unsigned)dst.sy) * (unsigned)sizeof(T) : 0u;
     }
 
     T ring[TD][NP][RING];
@@ -131,9 +146,13 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
             for (int i = 0; i < NP; ++i) pre[i] = g;
             return;
         }
-        const T* __restrict__ plane = (const T*)src.origin + (int64_t)(perz ? wrap_index(j, nz) : j) * src.sz;
+        const char* __restrict__ plane =
+            (const char*)((const T*)src.origin + (int64_t)(perz ? wrap_index(j, nz) : j) * src.sz);
 #pragma unroll
-        for (int i = 0; i < NP; ++i) pre[i] = blend(live[i], plane[soff[i]], g);
+        for (int i = 0; i < NP; ++i) {
+            const T v = *(const T*)(plane + soff[i]);
+            pre[i] = DXY ? blend(live[i], v, g) : v;
+        }
     };
 
     const int jstart = z0 - G;
@@ -159,7 +178,7 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
                 continue;
             }
             const T* L = &lds[k - 1][rb][GUARD];
-            T* out = (T*)dst.origin + (int64_t)zk * dst.sz;
+            char* out = (char*)((T*)dst.origin + (int64_t)zk * dst.sz);
             const bool zin = zk >= z0 && zk < zend;
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
@@ -177,9 +196,9 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
                 for (int o = 1; o <= R; ++o) v = fma(cf.c[4 * R + o], L[p + o * W], v);
 #pragma unroll
                 for (int o = 1; o <= R; ++o) v = fma(cf.c[5 * R + o], rk[(R + o + PH) % RING], v);
-                v = blend(live[i], v, g);
+                if (DXY) v = blend(live[i], v, g);
                 if (k == TD) {
-                    if (keep[i] && zin) __builtin_nontemporal_store(v, out + doff[i]);
+                    if (keep[i] && zin) __builtin_nontemporal_store(v, (T*)(out + doff[i]));
                 } else {
                     ring[k][i][PH] = v;   // level k's oldest plane is no longer read
                 }
@@ -197,9 +216,7 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
     };
 
     load_plane(jstart);
-    // Steps past jend (at most RING-1) only compute and publish values that
-    // nothing stores: every store is limited to z0 <= zk < zend.
-    for (int j = jstart; j <= jend; j += RING) unroll_steps<0, RING>(j, step);
+    for (int j = jstart; j <= jend; j += RING) unroll_steps<0, RING>(j, jend, step);
 }
 
 template <typename T, int R, int TD, int BX, int BY, int NT>
@@ -223,8 +240,12 @@ hipError_t run_star3d_flat(const SweepJob& j, int chunk, hipStream_t s) {
     if (nb64 > (1ll << 30)) return hipErrorInvalidConfiguration;
     const int nb = (int)nb64;
     const int nbp = padded_block_count(nb);
-    hipLaunchKernelGGL((k_star3d_flat<T, R, TD, BX, BY, NT>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, j.rule, cf,
-                       chunk, tiles_x, tiles_y, nb, nbp);
+    if (!j.rule.per[0] || !j.rule.per[1])
+        hipLaunchKernelGGL((k_star3d_flat<T, R, TD, BX, BY, NT, true>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst,
+                           j.rule, cf, chunk, tiles_x, tiles_y, nb, nbp);
+    else
+        hipLaunchKernelGGL((k_star3d_flat<T, R, TD, BX, BY, NT, false>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst,
+                           j.rule, cf, chunk, tiles_x, tiles_y, nb, nbp);
     return hipGetLastError();
 }
 
@@ -244,7 +265,6 @@ const Variant kStar3dFlat[] = {
     FSTAR(float, LOPE_F32, 1, 4, 64, 32, 1024, 256),
     FSTAR(float, LOPE_F32, 1, 4, 64, 16, 256, 256),
     FSTAR(float, LOPE_F32, 4, 1, 64, 32, 512, 128),
-    FSTAR(float, LOPE_F32, 4, 2, 64, 32, 1024, 128),
     FSTAR(double, LOPE_F64, 1, 3, 32, 32, 256, 32),
     FSTAR(double, LOPE_F64, 1, 3, 32, 32, 512, 32),
     FSTAR(double, LOPE_F64, 1, 3, 64, 16, 512, 32),

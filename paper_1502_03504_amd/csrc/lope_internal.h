@@ -79,6 +79,7 @@ int star3d_flat_variants(const Variant** out);
 int star3d_vec_variants(const Variant** out);
 int star3d_vtb_variants(const Variant** out);
 int plane2d_variants(const Variant** out);
+int plane2d_wave_variants(const Variant** out);
 
 // Variable-coefficient diffusion.
 hipError_t launch_var_forward(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa,
@@ -101,16 +102,15 @@ struct BatchGrid {
     int32_t pad[3];
 };
 
-// One tile of one grid: output columns [x0, x0 + tile width), rows [y0, y1).
+// One strip of one grid, swept by one wave: output columns
+// [x0, x0 + batch_strip_width(tdepth)), rows [y0, y1).
 struct BatchItem {
     int32_t grid;
     int32_t x0, y0, y1;
-    int32_t wide;         // 1: 512-wide tile, 0: 256-wide tile
-    int32_t pad;
 };
 
-// Output columns of a batch tile sweeping tdepth times per pass.
-int batch_tile_width(int tdepth, bool wide);
+// Output columns of a batch strip sweeping tdepth times per pass.
+int batch_strip_width(int tdepth);
 // One pass of tdepth sweeps over every listed tile; parity 0 reads src, 1 reads dst.
 hipError_t launch_batch_pass(const BatchGrid* grids, const BatchItem* items, int nitems, int tdepth, int parity,
                              int dtype, hipStream_t s);

@@ -1,0 +1,184 @@
+// One wavefront sweeping a strip of a 2D grid with a radius-1 stencil
+// (box: 9 taps, star: 5 taps), TD sweeps fused: the body shared by the
+// single-grid wave kernel and the batched kernel.
+//
+// The wave owns 64 consecutive columns of the grid (one per lane) and marches
+// down the rows [y0, yend) of its strip.  Its output columns are the middle
+// 64 - 2*TD, [x0, x0 + 64 - 2*TD): every fused sweep consumes one column of
+// halo on each side, and the x neighbours of a lane are the values of lanes
+// l-1 and l+1, moved across the wave with DPP wave shifts (the two outermost
+// lanes read a neighbour the wave does not hold; their values at higher
+// levels are never used by an output lane).  Each level k < TD keeps its last
+// three rows in registers with their left and right neighbours (nine values);
+// at march step j level 0 receives row j and level k computes row j - k from
+// level k-1's rows j-k-1 .. j-k+1, all in the same step (levels ascending).
+// The march is unrolled by three so every ring slot is a fixed register, and
+// rows are prefetched three steps ahead.  No LDS, no barriers.  Each point is
+// c0*v0 followed by fmas in lexicographic offset order (x fastest), the same
+// as every other kernel.
+//
+// Boundary rule: along a periodic axis the loaded column or row is the wrapped
+// one; a lane outside the interior along a Dirichlet x axis (DX) holds g at
+// every level (bit blend), and a row outside along a Dirichlet y axis (DY) is
+// g at every level (a wave-uniform choice).
+//
+// Every argument must be uniform across the wave, and all 64 lanes must be
+// active (the DPP shifts read every lane).
+#pragma once
+
+#include <type_traits>
+
+#include "lope_internal.h"
+
+namespace lope {
+
+constexpr int kDppWaveShr1 = 0x138;   // lane l receives lane l-1
+constexpr int kDppWaveShl1 = 0x130;   // lane l receives lane l+1
+
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ float wblend(unsigned m, float v, float g) {
+    return __uint_as_float((__float_as_uint(v) & m) | (__float_as_uint(g) & ~m));
+}
+__device__ __forceinline__ double wblend(unsigned long long m, double v, double g) {
+    const unsigned long long vb = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long gb = (unsigned long long)__double_as_longlong(g);
+    return __longlong_as_double((long long)((vb & m) | (gb & ~m)));
+}
+
+template <typename T>
+struct WMask {
+    typedef unsigned type;
+};
+template <>
+struct WMask<double> {
+    typedef unsigned long long type;
+};
+
+template <typename T>
+struct Coef9 {
+    T c[9];   // (ox + 1) + 3 * (oy + 1)
+};
+
+template <int P, int N, typename F>
+__device__ __forceinline__ void wave_steps(int j, F& f) {
+    if constexpr (P < N) {
+        f(j + P, std::integral_constant<int, P>{});
+        wave_steps<P + 1, N>(j, f);
+    }
+}
+
+template <typename T, int TD, bool BOX, bool DX, bool DY>
+__device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const DevGrid& dst, T g, const T (&c9)[9],
+                                                   int x0, int y0, int yend) {
+    typedef typename WMask<T>::type M;
+    constexpr int G = TD;
+    const int lane = threadIdx.x & 63;
+    const int nx = src.nx, ny = src.ny;
+    const int gx = x0 - G + lane;
+    const bool ox = gx < 0 || gx >= nx;
+    const int wx = DX ? min(max(gx, 0), nx - 1) : wrap_index(gx, nx);
+    const M live = (DX && ox) ? (M)0 : ~(M)0;
+    const bool keep = lane >= G && lane < 64 - G && gx < nx;
+    const unsigned coff = (unsigned)wx * (unsigned)sizeof(T);
+    const unsigned doff = keep ? (unsigned)gx * (unsigned)sizeof(T) : 0u;
+
+    // Rows are loaded in order, one per march step: a running (wrapped) row
+    // index and byte pointer avoid per-step multiplies and modulos.
+    const int64_t sbytes = src.sy * (int64_t)sizeof(T);
+    const char* const sbase = (const char*)src.origin;
+    int lj = y0 - G;                               // next row to load
+    int lw = DY ? lj : wrap_index(lj, ny);         // its wrapped index
+    const char* lp = sbase + (int64_t)lw * sbytes;
+    auto next_row = [&]() -> T {
+        T v = g;   // raw value: the x rule is applied when the row enters level 0
+        if (!DY || (lj >= 0 && lj < ny)) v = *(const T*)(lp + coff);
+        ++lj;
+        ++lw;
+        lp += sbytes;
+        if (!DY && lw == ny) {
+            lw = 0;
+            lp = sbase;
+        }
+        return v;
+    };
+
+    // ring[k][slot][0..2] = (left, centre, right) of a level-k row
+    T ring[TD][3][3];
+#pragma unroll
+    for (int k = 0; k < TD; ++k)
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) ring[k][s][t] = (T)0;
+
+    const int jstart = y0 - G;
+    const int jlast_load = yend - 1 + G;
+    const int jend = yend - 1 + TD;
+    T pf[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) pf[s] = (jstart + s <= jlast_load) ? next_row() : g;
+    // output row pointer of level TD, advanced one row per step
+    const int64_t dbytes = dst.sy * (int64_t)sizeof(T);
+    char* sp_out = (char*)dst.origin + (int64_t)(jstart - TD) * dbytes + doff;
+
+    auto push = [&](int k, int slot, T v) {
+        ring[k][slot][0] = wave_shift<kDppWaveShr1>(v);
+        ring[k][slot][1] = v;
+        ring[k][slot][2] = wave_shift<kDppWaveShl1>(v);
+    };
+
+    auto step = [&](int j, auto phase) {
+        constexpr int PH = decltype(phase)::value;
+        constexpr int S0 = (PH + 1) % 3, S1 = (PH + 2) % 3, S2 = PH;   // rows y-1, y, y+1 after the push
+        push(0, PH, DX ? wblend(live, pf[PH], g) : pf[PH]);
+        if (j + 3 <= jlast_load) pf[PH] = next_row();
+#pragma unroll
+        for (int k = 1; k <= TD; ++k) {
+            const int yk = j - k;
+            const T(*r)[3] = ring[k - 1];
+            T v;
+            if (BOX) {
+                v = c9[0] * r[S0][0];
+                v = fma(c9[1], r[S0][1], v);
+                v = fma(c9[2], r[S0][2], v);
+                v = fma(c9[3], r[S1][0], v);
+                v = fma(c9[4], r[S1][1], v);
+                v = fma(c9[5], r[S1][2], v);
+                v = fma(c9[6], r[S2][0], v);
+                v = fma(c9[7], r[S2][1], v);
+                v = fma(c9[8], r[S2][2], v);
+            } else {
+                v = c9[1] * r[S0][1];
+                v = fma(c9[3], r[S1][0], v);
+                v = fma(c9[4], r[S1][1], v);
+                v = fma(c9[5], r[S1][2], v);
+                v = fma(c9[7], r[S2][1], v);
+            }
+            if (DX) v = wblend(live, v, g);
+            if (DY && (yk < 0 || yk >= ny)) v = g;
+            if (k == TD) {
+                if (keep && yk >= y0 && yk < yend) __builtin_nontemporal_store(v, (T*)sp_out);
+                sp_out += dbytes;
+            } else {
+                push(k, PH, v);
+            }
+        }
+    };
+
+    // up to two steps past jend compute rows that nothing stores (stores are
+    // limited to y0 <= yk < yend, loads to rows <= jlast_load)
+    for (int j = jstart; j <= jend; j += 3) wave_steps<0, 3>(j, step);
+}
+
+}  // namespace lope

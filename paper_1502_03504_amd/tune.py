@@ -164,13 +164,19 @@ def register_cache(path=None) -> int:
         g.ndim = ndim
         g.h = radius
         g.dtype = _lib.LOPE_F64 if dt == "f64" else _lib.LOPE_F32
-        g.n[0] = 1 << bucket
-        g.n[1] = g.n[2] = 1
+        # a near-cube of 2^bucket points (planes small enough for every
+        # family's offset limits)
+        e = [0, 0, 0]
+        for a in range(bucket):
+            e[(ndim - 1 - a % ndim) if ndim > 1 else 0] += 1
+        n = [1 << e[0], 1 << e[1], 1 << e[2]]
+        for a in range(3):
+            g.n[a] = n[a] if a < ndim else 1
         g.stride[0] = 1
         # strides and origin in whole 128-byte lines, like Grid.allocate, so
         # vector variants accept the descriptor
-        g.stride[1] = (((1 << bucket) + 2 * radius + 63) // 64) * 64
-        g.stride[2] = g.stride[1] * (1 + 2 * radius)
+        g.stride[1] = ((g.n[0] + 2 * radius + 63) // 64) * 64 if ndim >= 2 else 0
+        g.stride[2] = g.stride[1] * (g.n[1] + 2 * radius) if ndim >= 3 else 0
         g.origin = 0x100000
         w = 2 * radius + 1
         import numpy as np
