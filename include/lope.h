@@ -179,18 +179,19 @@ int lope_iterate_tuned(const lope_grid* a, const lope_grid* b, const lope_stenci
 /* Sweeps until converged (section 3.2: the do-while loop around the sweep,
  * whose convergence test the paper leaves open).  After every sweep whose
  * count is a multiple of check_every, the residual max_x |u_t[x] - u_{t-1}[x]|
- * over the interior is formed in float64 (difference of the two stored
- * values, magnitude, maximum: independent of evaluation order, so exact);
- * the loop stops after the first checked sweep whose residual is <= tol, or
- * after max_steps sweeps.  Sweeps between checks are fused per pass as in
- * lope_iterate (tdepth, 0 = automatic); the checked sweep runs alone so that
- * both states are in memory.  A NaN residual never satisfies the test.
+ * over the interior is formed in float64 (difference of the two values,
+ * magnitude, maximum: independent of evaluation order, so exact); the loop
+ * stops after the first checked sweep whose residual is <= tol, or after
+ * max_steps sweeps.  Sweeps are fused per pass as in lope_iterate (tdepth,
+ * 0 = automatic); the pass that ends on a checked sweep reports the residual
+ * of its last sweep from values it computes anyway.  A NaN residual never
+ * satisfies the test.
  *
  * residual_scratch: DEVICE pointer to one 8-byte aligned double the call may
  * overwrite (caller-owned).  On return *steps_done is the number of sweeps
  * run, *residual the last residual formed (NaN if none), *result_index 0 if
- * the final state is in a, 1 if in b; when the last sweep was a checked one
- * the other buffer holds the state before it.  All three must not be NULL.
+ * the final state is in a, 1 if in b; the other buffer holds an earlier
+ * state.  All three must not be NULL.
  *
  * SYNCHRONOUS: the host waits on `stream` after every check to read the
  * residual, so the call cannot be recorded into a graph (a capturing stream

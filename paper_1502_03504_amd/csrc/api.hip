@@ -215,6 +215,7 @@ void build_job(SweepJob& j, const lope_grid* src, const lope_grid* dst, const lo
     j.src = dev_grid(src);
     j.dst = dev_grid(dst);
     j.rule = dev_rule(bc, src->ndim, reflect);
+    j.residual = nullptr;
     const int r = st->radius, w = 2 * r + 1;
     const int wy = src->ndim >= 2 ? w : 1, wz = src->ndim >= 3 ? w : 1;
     memset(j.dense, 0, sizeof j.dense);
@@ -368,6 +369,29 @@ Plan choose(const SweepJob& j, int tdepth_req, int variant_req, int chunk_req) {
     p.variant = 0;
     p.tdepth = 1;
     return p;
+}
+
+// A variant of `depth` sweeps per pass that reports the residual of its last
+// sweep (Variant::res): the tuned choice for that depth if it has one, else the
+// first fitting entry of the table.  0 if none fits.
+int residual_variant(const SweepJob& j, int depth, int* chunk) {
+    *chunk = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const int64_t pts = (int64_t)j.src.nx * j.src.ny * j.src.nz;
+        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts, depth));
+        if (it != g_tune.end() && it->second.variant > 0 && it->second.tdepth == depth) {
+            const Variant& v = registry().v[it->second.variant - 1];
+            if (v.res && variant_fits(v, j, depth)) {
+                *chunk = it->second.chunk;
+                return it->second.variant;
+            }
+        }
+    }
+    auto& R = registry().v;
+    for (size_t i = 0; i < R.size(); ++i)
+        if (R[i].res && variant_fits(R[i], j, depth)) return (int)i + 1;
+    return 0;
 }
 
 int iterate_impl(const lope_grid* a, const lope_grid* b, const lope_stencil* st, const lope_bc* bc,
@@ -601,6 +625,13 @@ int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stenci
     if (cap != hipStreamCaptureStatusNone)
         return fail(LOPE_ERR_UNSUPPORTED, "lope_iterate_until waits on the host; it cannot be captured");
     const DevGrid ga = dev_grid(a), gb = dev_grid(b);
+    // The last sweeps before each check run as one pass of a variant that also
+    // reports the residual of its last sweep (no extra pass over memory); with
+    // no such variant, the checked sweep runs alone and k_residual_max
+    // compares the two buffers.
+    static thread_local SweepJob rjob;
+    build_job(rjob, a, b, st, bc, false);
+    const int want = choose(rjob, tdepth, 0, 0).tdepth;
     int cur = 0;   // buffer holding the state: 0 = a, 1 = b
     int64_t done = 0;
     while (done < max_steps) {
@@ -612,19 +643,32 @@ int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stenci
             done = max_steps;
             break;
         }
-        if (to_check > 1) {
-            if ((rc = iterate_impl(cur ? b : a, cur ? a : b, st, bc, to_check - 1, tdepth, 0, 0, stream, &idx)))
+        int rd = (int)std::min<int64_t>(want, to_check), rv = 0, rchunk = 0;
+        for (; rd >= 1 && !(rv = residual_variant(rjob, rd, &rchunk)); --rd) {
+        }
+        const int last = rv ? rd : 1;   // sweeps of the checked pass
+        if (to_check > last) {
+            if ((rc = iterate_impl(cur ? b : a, cur ? a : b, st, bc, to_check - last, tdepth, 0, 0, stream, &idx)))
                 return rc;
             cur ^= idx;
         }
-        // the checked sweep alone, then the residual between the two buffers
-        if ((rc = iterate_impl(cur ? b : a, cur ? a : b, st, bc, 1, 1, 0, 0, stream, &idx))) return rc;
-        const DevGrid& prev = cur ? gb : ga;
-        const DevGrid& next = cur ? ga : gb;
-        cur ^= 1;
+        if (rv) {
+            build_job(rjob, cur ? b : a, cur ? a : b, st, bc, false);
+            rjob.residual = residual_scratch;
+            if ((e = launch_residual_zero(residual_scratch, s)) != hipSuccess) return hip_fail(e, "residual reset");
+            if ((rc = run_pass(rjob, rv, rchunk, s))) return rc;
+            rjob.residual = nullptr;
+            cur ^= 1;
+        } else {
+            // the checked sweep alone, then the residual between the two buffers
+            if ((rc = iterate_impl(cur ? b : a, cur ? a : b, st, bc, 1, 1, 0, 0, stream, &idx))) return rc;
+            const DevGrid& prev = cur ? gb : ga;
+            const DevGrid& next = cur ? ga : gb;
+            cur ^= 1;
+            if ((e = launch_residual_max(prev, next, a->dtype, residual_scratch, s)) != hipSuccess)
+                return hip_fail(e, "residual launch");
+        }
         done += to_check;
-        if ((e = launch_residual_max(prev, next, a->dtype, residual_scratch, s)) != hipSuccess)
-            return hip_fail(e, "residual launch");
         double r = 0.0;
         if ((e = hipMemcpyAsync(&r, residual_scratch, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)

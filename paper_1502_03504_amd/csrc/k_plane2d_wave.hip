@@ -7,18 +7,18 @@
 namespace lope {
 namespace {
 
-template <typename T, int TD, bool BOX, int NW, bool DX, bool DY>
+template <typename T, int TD, bool BOX, int NW, bool DX, bool DY, bool RES>
 __global__ void __launch_bounds__(NW * 64)
 k_plane2d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef9<T> cf, int chunk, int strips, int nwaves,
-               int nblocks_padded) {
+               int nblocks_padded, double* residual) {
     // the wave index is uniform across the wave: say so, so that rows, loop
     // bounds and the row rule stay scalar
     const int wave = xcd_logical_block(nblocks_padded) * NW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (wave >= nwaves) return;   // whole waves leave; the kernel has no barrier
     const int tx = wave % strips, ty = wave / strips;
     const int y0 = ty * chunk;
-    plane2d_wave_strip<T, TD, BOX, DX, DY>(src, dst, (T)rule.g, cf.c, tx * (64 - 2 * TD), y0,
-                                           min(y0 + chunk, src.ny));
+    plane2d_wave_strip<T, TD, BOX, DX, DY, RES>(src, dst, (T)rule.g, cf.c, tx * (64 - 2 * TD), y0,
+                                                min(y0 + chunk, src.ny), residual);
 }
 
 template <typename T, int TD, bool BOX, int NW>
@@ -38,24 +38,31 @@ hipError_t run_plane2d_wave(const SweepJob& j, int chunk, hipStream_t s) {
     const int nb = (nw + NW - 1) / NW;
     const int nbp = padded_block_count(nb);
     const bool dx = !j.rule.per[0], dy = !j.rule.per[1];
-#define LOPE_WAVE_LAUNCH(A, B)                                                                                 \
-    hipLaunchKernelGGL((k_plane2d_wave<T, TD, BOX, NW, A, B>), dim3(nbp), dim3(NW * 64), 0, s, j.src, j.dst, \
-                       j.rule, cf, chunk, strips, nw, nbp)
-    if (dx && dy)
-        LOPE_WAVE_LAUNCH(true, true);
-    else if (dx)
-        LOPE_WAVE_LAUNCH(true, false);
-    else if (dy)
-        LOPE_WAVE_LAUNCH(false, true);
-    else
-        LOPE_WAVE_LAUNCH(false, false);
+#define LOPE_WAVE_LAUNCH(A, B, C)                                                                                 \
+    hipLaunchKernelGGL((k_plane2d_wave<T, TD, BOX, NW, A, B, C>), dim3(nbp), dim3(NW * 64), 0, s, j.src, j.dst, \
+                       j.rule, cf, chunk, strips, nw, nbp, j.residual)
+#define LOPE_WAVE_RULE(C)                  \
+    if (dx && dy)                          \
+        LOPE_WAVE_LAUNCH(true, true, C);   \
+    else if (dx)                           \
+        LOPE_WAVE_LAUNCH(true, false, C);  \
+    else if (dy)                           \
+        LOPE_WAVE_LAUNCH(false, true, C);  \
+    else                                   \
+        LOPE_WAVE_LAUNCH(false, false, C)
+    if (j.residual) {
+        LOPE_WAVE_RULE(true);
+    } else {
+        LOPE_WAVE_RULE(false);
+    }
+#undef LOPE_WAVE_RULE
 #undef LOPE_WAVE_LAUNCH
     return hipGetLastError();
 }
 
 #define PWAVE(T, DT, TD, BOX, NW, CH)                                                                  \
     {"plane2dw_" #T "_r1_t" #TD "_nw" #NW "_" #BOX, FAM_PLANE2D, 2, 1, TD, DT, BOX, 64 - 2 * (TD), 0, \
-     (NW) * 64, CH, &run_plane2d_wave<T, TD, BOX, NW>}
+     (NW) * 64, CH, &run_plane2d_wave<T, TD, BOX, NW>, 1}
 
 const Variant kPlane2dWave[] = {
     PWAVE(float, LOPE_F32, 1, true, 4, 128),

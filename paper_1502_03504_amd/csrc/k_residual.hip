@@ -15,8 +15,6 @@ namespace {
 
 constexpr int kResThreads = 256;
 
-__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
-
 template <typename T>
 __global__ void __launch_bounds__(kResThreads)
 k_residual_max(DevGrid x, DevGrid y, unsigned long long* out) {
@@ -52,6 +50,11 @@ __global__ void k_zero_u64(unsigned long long* out) {
 }
 
 }  // namespace
+
+hipError_t launch_residual_zero(double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long*>(out));
+    return hipGetLastError();
+}
 
 hipError_t launch_residual_max(const DevGrid& x, const DevGrid& y, int dtype, double* out, hipStream_t s) {
     unsigned long long* o = reinterpret_cast<unsigned long long*>(out);

@@ -18,7 +18,10 @@
 // * global addresses are a per-plane base (wave-uniform) plus a 32-bit
 //   in-plane byte offset (the caller checks that planes fit 31 bits);
 // * on grids periodic in x and y no position holds g, and the blend is
-//   compiled out (DXY = false).
+//   compiled out (DXY = false);
+// * with RES, the pass also merges max |u_TD - u_(TD-1)| over its outputs
+//   (the change made by its last sweep, from values it holds anyway) into a
+//   device double, for the convergence test.
 //
 // The per-point sum is c0*v0 followed by fmas in lexicographic offset order
 // (z-R .. z-1, y-R .. y-1, x-R .. x+R, y+1 .. y+R, z+1 .. z+R), as in every
@@ -83,10 +86,10 @@ __device__ __forceinline__ void unroll_steps(int j, int jend, F& f) {
     }
 }
 
-template <typename T, int R, int TD, int BX, int BY, int NT, bool DXY>
+template <typename T, int R, int TD, int BX, int BY, int NT, bool DXY, bool RES>
 __global__ void __launch_bounds__(NT, (FlatShape<T, R, TD, BX, BY, NT>::WAVES_PER_EU))
 k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chunk, int tiles_x, int tiles_y,
-              int nblocks, int nblocks_padded) {
+              int nblocks, int nblocks_padded, double* residual) {
     typedef FlatShape<T, R, TD, BX, BY, NT> S;
     constexpr int G = S::G, W = S::W, H = S::H, NPOS = S::NPOS, NP = S::NP, RING = S::RING;
     constexpr int GUARD = S::GUARD, PLANE = S::PLANE;
@@ -161,6 +164,7 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
 
     // One march step at ring phase PH: ring slot (s + PH) % RING holds the
     // plane at logical position s (0 = oldest) of every level's window.
+    double rmax = 0.0;   // RES: max |last sweep - the sweep before| over this thread's outputs
     auto step = [&](int j, auto phase) {
         constexpr int PH = decltype(phase)::value;
         const int rb = (j & 1) ^ 1;
@@ -198,7 +202,11 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
                 for (int o = 1; o <= R; ++o) v = fma(cf.c[5 * R + o], rk[(R + o + PH) % RING], v);
                 if (DXY) v = blend(live[i], v, g);
                 if (k == TD) {
-                    if (keep[i] && zin) __builtin_nontemporal_store(v, (T*)(out + doff[i]));
+                    if (keep[i] && zin) {
+                        __builtin_nontemporal_store(v, (T*)(out + doff[i]));
+                        // level TD-1 at this point is the state before the last sweep
+                        if (RES) rmax = nan_max(rmax, fabs((double)v - (double)rk[(R + PH) % RING]));
+                    }
                 } else {
                     ring[k][i][PH] = v;   // level k's oldest plane is no longer read
                 }
@@ -217,6 +225,7 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
 
     load_plane(jstart);
     for (int j = jstart; j <= jend; j += RING) unroll_steps<0, RING>(j, jend, step);
+    if (RES) residual_merge(rmax, residual);
 }
 
 template <typename T, int R, int TD, int BX, int BY, int NT>
@@ -240,18 +249,28 @@ hipError_t run_star3d_flat(const SweepJob& j, int chunk, hipStream_t s) {
     if (nb64 > (1ll << 30)) return hipErrorInvalidConfiguration;
     const int nb = (int)nb64;
     const int nbp = padded_block_count(nb);
-    if (!j.rule.per[0] || !j.rule.per[1])
-        hipLaunchKernelGGL((k_star3d_flat<T, R, TD, BX, BY, NT, true>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst,
-                           j.rule, cf, chunk, tiles_x, tiles_y, nb, nbp);
-    else
-        hipLaunchKernelGGL((k_star3d_flat<T, R, TD, BX, BY, NT, false>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst,
-                           j.rule, cf, chunk, tiles_x, tiles_y, nb, nbp);
+    const bool dxy = !j.rule.per[0] || !j.rule.per[1];
+#define LOPE_FLAT_LAUNCH(A, B)                                                                                \
+    hipLaunchKernelGGL((k_star3d_flat<T, R, TD, BX, BY, NT, A, B>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, \
+                       j.rule, cf, chunk, tiles_x, tiles_y, nb, nbp, j.residual)
+    if (j.residual) {
+        if (dxy)
+            LOPE_FLAT_LAUNCH(true, true);
+        else
+            LOPE_FLAT_LAUNCH(false, true);
+    } else {
+        if (dxy)
+            LOPE_FLAT_LAUNCH(true, false);
+        else
+            LOPE_FLAT_LAUNCH(false, false);
+    }
+#undef LOPE_FLAT_LAUNCH
     return hipGetLastError();
 }
 
 #define FSTAR(T, DT, R, TD, BX, BY, NT, CH)                                                      \
     {"star3df_" #T "_r" #R "_t" #TD "_" #BX "x" #BY "_nt" #NT, FAM_STAR3D_FLAT, 3, R, TD, DT, 0, \
-     BX, BY, NT, CH, &run_star3d_flat<T, R, TD, BX, BY, NT>}
+     BX, BY, NT, CH, &run_star3d_flat<T, R, TD, BX, BY, NT>, 1}
 
 const Variant kStar3dFlat[] = {
     FSTAR(float, LOPE_F32, 1, 3, 64, 32, 512, 128),

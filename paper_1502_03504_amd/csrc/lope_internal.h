@@ -46,6 +46,8 @@ struct SweepJob {
     int8_t off[kMaxTaps][3];        // non-zero taps, lexicographic order
     double c[kMaxTaps];             // coefficients rounded to the grid dtype
     double dense[729];              // full (2r+1)^d table, rounded, x fastest
+    double* residual;               // device, or null: variants with `res` merge into it the
+                                    // max |last sweep - the sweep before| of their outputs
 };
 
 // ---- launchers (return hipSuccess or the launch error) ----
@@ -57,6 +59,8 @@ hipError_t launch_accumulate(const DevGrid& part, int part_dtype, const DevGrid&
 hipError_t launch_gbar(const SweepJob& j, double* out, hipStream_t s);
 // *out (device) = max over the interior of |y - x| in float64 (x, y same extents)
 hipError_t launch_residual_max(const DevGrid& x, const DevGrid& y, int dtype, double* out, hipStream_t s);
+// *out (device) = +0.0, the identity of the residual maximum
+hipError_t launch_residual_zero(double* out, hipStream_t s);
 
 // Tuned kernel families.
 enum Family { FAM_GENERIC = 0, FAM_STAR3D = 1, FAM_PLANE2D = 2, FAM_STAR3D_VEC = 3, FAM_STAR3D_FLAT = 4 };
@@ -71,6 +75,7 @@ struct Variant {
     int bx, by, nt;                 // output tile (x, y) and threads per workgroup
     int default_chunk;
     VariantFn fn;
+    int res;                        // 1: honours SweepJob::residual
 };
 
 // Registries filled by each kernel file.
@@ -120,6 +125,20 @@ __device__ __forceinline__ int wrap_index(int i, int n) {
     if ((unsigned)i < (unsigned)n) return i;
     int m = i % n;
     return m < 0 ? m + n : m;
+}
+
+// Maximum that propagates NaN (a NaN operand wins and stays).
+__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// Merge a per-lane maximum of non-negative doubles (or NaN) into *out: a
+// reduction across the wave, then one 64-bit unsigned atomic max per wave on
+// the bit pattern (non-negative doubles and the positive NaN order like their
+// bits).  Every lane of the wave must call it.
+__device__ __forceinline__ void residual_merge(double m, double* out) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0)
+        atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(m));
 }
 
 // Barrier that orders LDS traffic only: outstanding global loads (prefetches)

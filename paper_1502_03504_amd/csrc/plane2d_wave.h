@@ -12,8 +12,9 @@
 // three rows in registers with their left and right neighbours (nine values);
 // at march step j level 0 receives row j and level k computes row j - k from
 // level k-1's rows j-k-1 .. j-k+1, all in the same step (levels ascending).
-// The march is unrolled by three so every ring slot is a fixed register, and
-// rows are prefetched three steps ahead.  No LDS, no barriers.  Each point is
+// The march is unrolled by six so every ring slot is a fixed register, and
+// rows are prefetched six steps ahead (the loads in flight per wave are what
+// keeps HBM busy: the wave has no other source of memory parallelism).  No LDS, no barriers.  Each point is
 // c0*v0 followed by fmas in lexicographic offset order (x fastest), the same
 // as every other kernel.
 //
@@ -21,6 +22,9 @@
 // one; a lane outside the interior along a Dirichlet x axis (DX) holds g at
 // every level (bit blend), and a row outside along a Dirichlet y axis (DY) is
 // g at every level (a wave-uniform choice).
+//
+// With RES the strip also merges max |u_TD - u_(TD-1)| over its outputs (the
+// change made by its last sweep) into the device double `residual`.
 //
 // Every argument must be uniform across the wave, and all 64 lanes must be
 // active (the DPP shifts read every lane).
@@ -70,17 +74,19 @@ struct Coef9 {
     T c[9];   // (ox + 1) + 3 * (oy + 1)
 };
 
+// f(j + P, step P) for P = 0 .. N-1 while j + P <= jend (a wave-uniform bound)
 template <int P, int N, typename F>
-__device__ __forceinline__ void wave_steps(int j, F& f) {
+__device__ __forceinline__ void wave_steps(int j, int jend, F& f) {
     if constexpr (P < N) {
+        if (j + P > jend) return;
         f(j + P, std::integral_constant<int, P>{});
-        wave_steps<P + 1, N>(j, f);
+        wave_steps<P + 1, N>(j, jend, f);
     }
 }
 
-template <typename T, int TD, bool BOX, bool DX, bool DY>
+template <typename T, int TD, bool BOX, bool DX, bool DY, bool RES = false>
 __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const DevGrid& dst, T g, const T (&c9)[9],
-                                                   int x0, int y0, int yend) {
+                                                   int x0, int y0, int yend, double* residual = nullptr) {
     typedef typename WMask<T>::type M;
     constexpr int G = TD;
     const int lane = threadIdx.x & 63;
@@ -125,9 +131,11 @@ __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const Dev
     const int jstart = y0 - G;
     const int jlast_load = yend - 1 + G;
     const int jend = yend - 1 + TD;
-    T pf[3];
+    // rows are loaded PF march steps ahead (PF a multiple of the ring length)
+    constexpr int PF = 6;
+    T pf[PF];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) pf[s] = (jstart + s <= jlast_load) ? next_row() : g;
+    for (int s = 0; s < PF; ++s) pf[s] = (jstart + s <= jlast_load) ? next_row() : g;
     // output row pointer of level TD, advanced one row per step
     const int64_t dbytes = dst.sy * (int64_t)sizeof(T);
     char* sp_out = (char*)dst.origin + (int64_t)(jstart - TD) * dbytes + doff;
@@ -138,11 +146,13 @@ __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const Dev
         ring[k][slot][2] = wave_shift<kDppWaveShl1>(v);
     };
 
+    double rmax = 0.0;   // RES: max |last sweep - the sweep before| over this lane's outputs
     auto step = [&](int j, auto phase) {
-        constexpr int PH = decltype(phase)::value;
+        constexpr int PQ = decltype(phase)::value;   // 0 .. PF-1
+        constexpr int PH = PQ % 3;                    // ring phase
         constexpr int S0 = (PH + 1) % 3, S1 = (PH + 2) % 3, S2 = PH;   // rows y-1, y, y+1 after the push
-        push(0, PH, DX ? wblend(live, pf[PH], g) : pf[PH]);
-        if (j + 3 <= jlast_load) pf[PH] = next_row();
+        push(0, PH, DX ? wblend(live, pf[PQ], g) : pf[PQ]);
+        if (j + PF <= jlast_load) pf[PQ] = next_row();
 #pragma unroll
         for (int k = 1; k <= TD; ++k) {
             const int yk = j - k;
@@ -168,7 +178,11 @@ __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const Dev
             if (DX) v = wblend(live, v, g);
             if (DY && (yk < 0 || yk >= ny)) v = g;
             if (k == TD) {
-                if (keep && yk >= y0 && yk < yend) __builtin_nontemporal_store(v, (T*)sp_out);
+                if (keep && yk >= y0 && yk < yend) {
+                    __builtin_nontemporal_store(v, (T*)sp_out);
+                    // the centre of level TD-1 is the state before the last sweep
+                    if (RES) rmax = nan_max(rmax, fabs((double)v - (double)r[S1][1]));
+                }
                 sp_out += dbytes;
             } else {
                 push(k, PH, v);
@@ -176,9 +190,8 @@ __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const Dev
         }
     };
 
-    // up to two steps past jend compute rows that nothing stores (stores are
-    // limited to y0 <= yk < yend, loads to rows <= jlast_load)
-    for (int j = jstart; j <= jend; j += 3) wave_steps<0, 3>(j, step);
+    for (int j = jstart; j <= jend; j += PF) wave_steps<0, PF>(j, jend, step);
+    if (RES) residual_merge(rmax, residual);
 }
 
 }  // namespace lope

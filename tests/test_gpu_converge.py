@@ -40,6 +40,12 @@ def _max_diff(x, y):
     return float((x.double() - y.double()).abs().max())
 
 
+def _plain(u0, h, st, bc, n):
+    """The grid holding the state after n sweeps of lope_iterate."""
+    a, b = grid_from(u0, h), empty_grid(u0.shape, h, u0.dtype)
+    return (a, b)[L.lope_iterate(a, b, st, bc, n)]
+
+
 CASES = [
     ("heat2d_f64_dirichlet", (40, 56), np.float64, lambda: synth.heat_star(2, 0.2), (D, D), 0.0, 3),
     ("heat3d_f32_periodic", (20, 24, 36), np.float32, lambda: synth.heat_star(3, 0.125), (P, P, P), 0.0, 4),
@@ -67,8 +73,8 @@ def test_matches_oracle(name, shape, dtype, mk, kinds, g, m):
     assert abs(r - want_res) <= 2 * TOL[dtype] * steps * float(np.abs(want_u).max()), (r, want_res)
     out = (a, b)[idx]
     assert rel_err(out.numpy(), want_u) <= TOL[dtype] * steps, name
-    # the other buffer holds the state before the checked sweep: the residual is exact
-    assert r == _max_diff(out.interior(), (b, a)[idx].interior())
+    # the residual is exact: the max change between plain runs of steps-1 and steps sweeps
+    assert r == _max_diff(out.interior(), _plain(u0, h, st, (kinds, g), steps - 1).interior())
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -80,6 +86,12 @@ def test_residual_is_exact_and_state_equals_plain_iteration(dtype):
     idx, steps, r = L.lope_iterate_until(a, b, st, (P, D, P), 1, 1, -1.0)
     assert (idx, steps) == (1, 1)
     assert r == _max_diff(b.interior(), torch.from_numpy(u0).cuda())
+    # fused checked passes (the residual comes from inside the pass) at every depth
+    for tdepth in (1, 2, 3, 4):
+        a, b = grid_from(u0, 1), empty_grid(u0.shape, 1, dtype)
+        idx, steps, r = L.lope_iterate_until(a, b, st, (P, D, P), 12, 6, -1.0, tdepth=tdepth)
+        assert steps == 12
+        assert r == _max_diff((a, b)[idx].interior(), _plain(u0, 1, st, (P, D, P), 11).interior()), tdepth
     # a run that stops on a check: same values as lope_iterate for that count
     for tdepth in (0, 1, 3):
         a, b = grid_from(u0, 1), empty_grid(u0.shape, 1, dtype)
@@ -129,19 +141,22 @@ def test_special_cases():
 
 
 def test_heat3d_512_f32_properties():
-    """Full size, checks every 100 sweeps: the residual equals the max change
-    between the two buffers exactly, and the state equals lope_iterate's for
-    the same sweep count, bit for bit."""
+    """Full size, checks every 100 sweeps: the state equals lope_iterate's for
+    the same sweep count, bit for bit, and the residual equals the max change
+    made by the last sweep exactly."""
     case = synth.case_heat3d(n=512, dtype=np.float32, steps=1000)
     a = grid_from(case.field, 1)
     b = a.empty_like()
     idx, steps, r = L.lope_iterate_until(a, b, case.stencil, case.bc, 1000, 100, 1e-5)
     assert steps % 100 == 0 and 0 < steps <= 1000
-    out, other = (a, b)[idx], (b, a)[idx]
-    assert r == _max_diff(out.interior(), other.interior())
     assert steps == 1000 or r <= 1e-5
-    del other
+    out = (a, b)[idx]
+    # same values as lope_iterate for that count, and the residual is exact
     c = grid_from(case.field, 1)
     d = c.empty_like()
-    j = L.lope_iterate(c, d, case.stencil, case.bc, steps)
-    assert torch.equal(out.interior(), (c, d)[j].interior())
+    j = L.lope_iterate(c, d, case.stencil, case.bc, steps - 1)
+    prev = (c, d)[j]
+    nxt = (d, c)[j]
+    L.lope_apply(prev, nxt, case.stencil, case.bc)
+    assert torch.equal(out.interior(), nxt.interior())
+    assert r == _max_diff(nxt.interior(), prev.interior())
