@@ -10,7 +10,8 @@ Everything here is the plain definition of what the method computes, written
 for a reader to check against the paper by eye, in float64 arithmetic with the
 state rounded to the grid dtype after every sweep:
 
-* ``stencil``   — halo rule, sweep, iteration (fixed count or until a
+* ``stencil``   — halo widths (symmetric or per-axis left/right), halo rule,
+  stencil reach, sweep, iteration (fixed count or until a
   convergence test holds), windowed sampling, adjoint;
 * ``diffusion`` — the variable-coefficient diffusion step and its gradient.
 
@@ -19,7 +20,8 @@ closed forms, invariants, library spectral routines or brute force; none is
 "parity unpinned".
 """
 from .stencil import (  # noqa: F401
-    rule_extend, halo_fill, sweep, iterate, iterate_until, sweep_at, adjoint, result_index,
+    rule_extend, halo_widths, halo_fill, stencil_reach, sweep, iterate, iterate_until, sweep_at, adjoint,
+    result_index,
 )
 from .diffusion import (  # noqa: F401
     diffusion_step, diffusion_forward, diffusion_loss, diffusion_gradient,

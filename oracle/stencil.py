@@ -81,17 +81,56 @@ def rule_extend(u: np.ndarray, w: int, kinds, g: float) -> np.ndarray:
     return _gather(u, [(-w, n + w) for n in u.shape], kinds, float(g))
 
 
-def halo_fill(u: np.ndarray, h: int, kinds, g: float) -> np.ndarray:
-    """Padded array (interior plus h halo cells per side) in u's dtype.
+def halo_widths(h, ndim: int):
+    """Per paper axis (x first) the halo widths (left/below, right/above).
+
+    ``h`` is one width for both sides of every axis, or a sequence of
+    (lo, hi) pairs, one per paper axis: the M:*:N halo of section 2.2 (M
+    cells to the left, N to the right) given for each dimension.
+    """
+    if np.ndim(h) == 0:
+        return [(int(h), int(h))] * ndim
+    w = [(int(lo), int(hi)) for lo, hi in h]
+    if len(w) != ndim or min(min(p) for p in w) < 0:
+        raise ValueError("one (lo, hi) pair of non-negative widths per axis")
+    return w
+
+
+def halo_fill(u: np.ndarray, h, kinds, g: float) -> np.ndarray:
+    """Padded array (interior plus the halo cells of every side) in u's dtype.
 
     This is what a halo transfer leaves in storage on one device: the interior
     unchanged and every halo cell set by the boundary rule, g rounded to the
-    grid dtype.
+    grid dtype.  ``h`` as in halo_widths (symmetric or per-axis lo/hi).
     """
     if u.size == 0:
         raise ValueError("an empty interior has no halo values to copy")
     gd = float(np.asarray(g, dtype=u.dtype))
-    return rule_extend(u, h, kinds, gd).astype(u.dtype)
+    w = halo_widths(h, u.ndim)
+    d = u.ndim
+    ranges = [(-w[d - 1 - npax][0], u.shape[npax] + w[d - 1 - npax][1]) for npax in range(d)]
+    return _gather(u, ranges, kinds, gd).astype(u.dtype)
+
+
+def stencil_reach(coeffs: np.ndarray, dtype=np.float64):
+    """Per paper axis (x first) how far the taps reach: (lo, hi) = the largest
+    offset toward lower / higher indices over the taps whose coefficient is
+    non-zero once rounded to ``dtype``.  A sweep reads exactly the halo cells
+    within this reach, so the halo must be at least this wide on each side
+    (section 3.5); a one-sided stencil needs a halo on one side only."""
+    c = np.asarray(coeffs, dtype=np.float64).astype(dtype)
+    r = _radius(c)
+    d = c.ndim
+    nz = np.argwhere(c != 0)
+    out = []
+    for a in range(d):
+        npax = d - 1 - a
+        if len(nz) == 0:
+            out.append((0, 0))
+            continue
+        offs = nz[:, npax] - r
+        out.append((max(0, int(-offs.min())), max(0, int(offs.max()))))
+    return out
 
 
 def _taps(coeffs: np.ndarray, dtype):
