@@ -29,10 +29,11 @@
  *     structural validation runs before any HIP call; on error nothing has
  *     been enqueued.  No exception crosses the ABI, nothing calls exit(), and
  *     there is no CPU fallback.  lope_last_error() gives a thread-local text.
- *   - Memory layout of a grid: padded storage with h halo cells on each side
- *     of every used axis; x (paper axis 0, the first index) is contiguous.
- *     Element (x, y, z), with -h <= x < n[0]+h etc., lives at
- *     origin + x + y*stride[1] + z*stride[2] (in elements).
+ *   - Memory layout of a grid: padded storage with halo cells on each side of
+ *     every used axis (h on both sides, or per-axis left/right widths); x
+ *     (paper axis 0, the first index) is contiguous.  Element (x, y, z), with
+ *     -lo[0] <= x < n[0]+hi[0] etc., lives at origin + x + y*stride[1] +
+ *     z*stride[2] (in elements).
  */
 #ifndef LOPE_H
 #define LOPE_H
@@ -48,7 +49,7 @@ typedef enum lope_status {
     LOPE_OK = 0,
     LOPE_ERR_INVALID_ARG = -1,    /* null pointer, bad ndim/extent/stride/dtype, mismatched grids,
                                      pointer not device memory, or storage outside its allocation */
-    LOPE_ERR_HALO_TOO_SMALL = -2, /* stencil radius larger than the halo width h (section 3.5) */
+    LOPE_ERR_HALO_TOO_SMALL = -2, /* stencil reaches beyond the halo on some side (section 3.5) */
     LOPE_ERR_ALIAS = -3,          /* source and destination interiors overlap (section 2.2, 3.5) */
     LOPE_ERR_UNSUPPORTED = -4,    /* valid request this build does not implement (see each call) */
     LOPE_ERR_NO_DEVICE = -5,      /* no usable GPU (or LOPE_FORCE_NO_DEVICE=1 in the environment) */
@@ -72,22 +73,35 @@ typedef enum lope_bc_kind {
 
 /* A padded grid (section 2.2 halo region; section 3.2 padded allocation).
  *   ndim    1..3.
- *   h       halo width in cells, the same on both sides of every used axis, >= 0.
+ *   h       halo width in cells, the same on both sides of every used axis, >= 0
+ *           (used when halo_mode is 0).
  *   dtype   lope_dtype.
+ *   halo_mode  0: width h on both sides of every used axis;
+ *           1: per-axis widths hlo[a] (left/below) and hhi[a] (right/above), the
+ *           M:*:N halo of section 2.2; each >= 0, and 0 on unused axes.
  *   n[a]    interior extent of axis a (a = 0 is x); >= 0; axes >= ndim must be 1.
  *           An interior with a zero extent is empty and every call on it is a no-op.
- *   stride  element strides; stride[0] must be 1, stride[1] >= n[0]+2h,
- *           stride[2] >= stride[1]*(n[1]+2h) (rows and planes do not overlap).
+ *   stride  element strides; stride[0] must be 1, stride[1] >= n[0] + lo[0] + hi[0],
+ *           stride[2] >= stride[1]*(n[1] + lo[1] + hi[1]) (rows and planes do not
+ *           overlap), with lo/hi the halo widths of the axis.
  *   origin  device pointer to interior element (0,0,0).  The whole padded box
- *           must lie inside one device allocation (checked). */
+ *           must lie inside one device allocation (checked).
+ * A stencil may be applied to a grid when, on every axis and side, the halo is
+ * at least as wide as the stencil reaches (the largest offset of a tap whose
+ * coefficient is non-zero once rounded to the grid type; section 3.5), else
+ * LOPE_ERR_HALO_TOO_SMALL: a one-sided stencil needs a halo on one side only.
+ * The sweeps never read the stored halo (they apply the rule while loading);
+ * the widths matter for validation and for lope_halo_fill. */
 typedef struct lope_grid {
     int32_t ndim;
     int32_t h;
     int32_t dtype;
-    int32_t reserved;
+    int32_t halo_mode;
     int64_t n[3];
     int64_t stride[3];
     void* origin;
+    int32_t hlo[3];
+    int32_t hhi[3];
 } lope_grid;
 
 /* Boundary rule (section 3.2, BC argument of the halo transfer).  kind[a] for
@@ -145,9 +159,9 @@ int lope_get_device(int ordinal, int* out);
 
 /* ---- halo ---------------------------------------------------------------- */
 
-/* Fill the stored halo of g from its own interior with the boundary rule
- * (section 3.2, the halo transfer on one device).  Only halo cells are
- * written; the interior is read.  The sweeps below do NOT need this: they
+/* Fill the stored halo of g (every side, its own width) from its own interior
+ * with the boundary rule (section 3.2, the halo transfer on one device).
+ * Only halo cells are written; the interior is read.  The sweeps below do NOT need this: they
  * apply the rule while loading, so the stored halo is never read by them. */
 int lope_halo_fill(const lope_grid* g, const lope_bc* bc, void* stream);
 
@@ -155,8 +169,9 @@ int lope_halo_fill(const lope_grid* g, const lope_bc* bc, void* stream);
 
 /* One sweep (section 3.2, do concurrent over the interior calling the local
  * element function): dst interior = S(B(src)).  src is never written; the
- * halo of dst is never written.  Requires radius <= src->h, equal ndim,
- * extents and dtype, and non-overlapping interiors. */
+ * halo of dst is never written.  Requires src's halo to cover the stencil's
+ * reach on every side, equal ndim, extents and dtype, and non-overlapping
+ * interiors. */
 int lope_apply(const lope_grid* src, const lope_grid* dst, const lope_stencil* st,
                const lope_bc* bc, void* stream);
 
@@ -165,8 +180,8 @@ int lope_apply(const lope_grid* src, const lope_grid* dst, const lope_stencil* s
  * initial state is a's interior.  Several sweeps may be fused per pass over
  * memory (tdepth, 0 = automatic); the result is identical.  *result_index is
  * set to 0 if the final state is in a, 1 if in b (n_steps mod 2 when one
- * sweep runs per pass).  Both grids need h >= radius.  result_index must not
- * be NULL. */
+ * sweep runs per pass).  Both grids' halos must cover the stencil's reach.
+ * result_index must not be NULL. */
 int lope_iterate(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
                  const lope_bc* bc, int64_t n_steps, int32_t tdepth, void* stream,
                  int32_t* result_index);
@@ -207,7 +222,8 @@ int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stenci
  * rule (periodic axes wrap; Dirichlet halo cells contribute zero).  If
  * gbar_dirichlet is not NULL it is a DEVICE pointer to one double that
  * receives (overwritten) dL/dg = sum_x ybar[x] * (sum of c_o over the taps of
- * x that read a Dirichlet halo cell). */
+ * x that read a Dirichlet halo cell).  The reflected stencil reaches the other
+ * way: ybar's halo must cover the forward reach mirrored (left <-> right). */
 int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_stencil* st,
                        const lope_bc* bc, double* gbar_dirichlet, void* stream);
 
@@ -215,7 +231,7 @@ int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_
 
 /* dst = src + dt * div(kappa grad src) with arithmetic-mean faces (see
  * lope_varcoef).  3D only, every axis periodic (else LOPE_ERR_UNSUPPORTED);
- * h >= 1 on src and kappa. */
+ * a halo of at least 1 on both sides of every axis of src and kappa. */
 int lope_apply_var(const lope_grid* src, const lope_grid* dst, const lope_varcoef* vc,
                    const lope_bc* bc, void* stream);
 

@@ -62,59 +62,79 @@ def _align(v: int, a: int) -> int:
     return (v + a - 1) // a * a
 
 
-class Grid:
-    """A padded grid in device memory: interior plus h halo cells per side.
+def _halo_pairs(h, ndim: int):
+    """Per paper axis (x first) the (left, right) halo widths: h is one width
+    for both sides of every axis, or a sequence of (lo, hi) pairs (the M:*:N
+    halo of section 2.2, per dimension)."""
+    if np.ndim(h) == 0:
+        return [(int(h), int(h))] * ndim
+    w = [(int(lo), int(hi)) for lo, hi in h]
+    if len(w) != ndim or min(min(p) for p in w) < 0:
+        raise ValueError("one (lo, hi) pair of non-negative halo widths per axis")
+    return w
 
+
+class Grid:
+    """A padded grid in device memory: interior plus halo cells on each side.
+
+    ``h`` is one halo width for both sides of every axis, or a sequence of
+    (lo, hi) widths per paper axis, x first (left/right, below/above, ...).
     Storage layout (the padded allocation of section 3.2, x contiguous): each
-    row starts ``lead`` elements before interior x = 0 (lead >= h, rounded so
-    the interior row start is 128-byte aligned), rows are ``sy`` elements apart
-    (a multiple of 128 bytes) and planes ``sz`` apart.
+    row starts ``lead`` elements before interior x = 0 (lead >= the left x
+    halo, rounded so the interior row start is 128-byte aligned), rows are
+    ``sy`` elements apart (a multiple of 128 bytes) and planes ``sz`` apart.
     """
 
-    def __init__(self, storage: torch.Tensor, shape, h: int, lead: int, sy: int, sz: int):
+    def __init__(self, storage: torch.Tensor, shape, h, lead: int, sy: int, sz: int):
         self.storage = storage
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
-        self.h = int(h)
+        d = self.ndim
+        self.halo = _halo_pairs(h, d)                       # per paper axis, x first
+        self.symmetric = np.ndim(h) == 0
+        self.h = int(h) if self.symmetric else max(max(p) for p in self.halo)
         self.lead = int(lead)
         self.sy = int(sy)
         self.sz = int(sz)
-        d = self.ndim
-        self.offset = self.lead + (self.h * self.sy if d >= 2 else 0) + (self.h * self.sz if d >= 3 else 0)
+        lo = [p[0] for p in self.halo] + [0] * (3 - d)
+        hi = [p[1] for p in self.halo] + [0] * (3 - d)
+        self.offset = self.lead + (lo[1] * self.sy if d >= 2 else 0) + (lo[2] * self.sz if d >= 3 else 0)
         if storage.dim() != 1:
             raise ValueError("storage must be a flat tensor")
         nx = self.shape[-1]
-        if self.lead < self.h or (d >= 2 and self.sy < self.lead + nx + self.h) or \
-                (d >= 3 and self.sz < self.sy * (self.shape[-2] + 2 * self.h)):
+        if self.lead < lo[0] or (d >= 2 and self.sy < self.lead + nx + hi[0]) or \
+                (d >= 3 and self.sz < self.sy * (self.shape[-2] + lo[1] + hi[1])):
             raise ValueError("strides do not hold the padded rows/planes")
-        last = self.offset + nx - 1 + self.h
+        last = self.offset + nx - 1 + hi[0]
         if d >= 2:
-            last += (self.shape[-2] - 1 + self.h) * self.sy
+            last += (self.shape[-2] - 1 + hi[1]) * self.sy
         if d >= 3:
-            last += (self.shape[-3] - 1 + self.h) * self.sz
-        first = self.offset - self.h - (self.h * self.sy if d >= 2 else 0) - (self.h * self.sz if d >= 3 else 0)
+            last += (self.shape[-3] - 1 + hi[2]) * self.sz
+        first = self.offset - lo[0] - (lo[1] * self.sy if d >= 2 else 0) - (lo[2] * self.sz if d >= 3 else 0)
         if min(self.shape) > 0 and (first < 0 or last >= storage.numel()):
             raise ValueError("storage of %d elements does not hold the padded box" % storage.numel())
 
     # ---- construction ----
     @classmethod
-    def allocate(cls, shape, h: int, dtype=torch.float32, device="cuda", halo_src=None, fill=0.0):
-        """New padded grid; with ``halo_src`` (a tensor or Grid) its interior is
-        copied in, like allocating with HALO_SRC in section 3.2."""
+    def allocate(cls, shape, h, dtype=torch.float32, device="cuda", halo_src=None, fill=0.0):
+        """New padded grid (h: one width, or (lo, hi) per paper axis); with
+        ``halo_src`` (a tensor or Grid) its interior is copied in, like
+        allocating with HALO_SRC in section 3.2."""
         shape = tuple(int(s) for s in shape)
         if not 1 <= len(shape) <= 3:
             raise ValueError("1..3 dimensions")
+        d = len(shape)
+        w = _halo_pairs(h, d) + [(0, 0)] * (3 - d)
         esize = torch.empty((), dtype=dtype).element_size()
         a = _ALIGN_BYTES // esize
         nx = shape[-1]
-        lead = _align(h, a) if h > 0 else 0
-        sy = _align(lead + nx + h, a)
-        d = len(shape)
+        lead = _align(w[0][0], a) if w[0][0] > 0 else 0
+        sy = _align(lead + nx + w[0][1], a)
         ny = shape[-2] if d >= 2 else 1
         nz = shape[-3] if d >= 3 else 1
-        rows = (ny + 2 * h) if d >= 2 else 1
+        rows = (ny + w[1][0] + w[1][1]) if d >= 2 else 1
         sz = sy * rows
-        planes = (nz + 2 * h) if d >= 3 else 1
+        planes = (nz + w[2][0] + w[2][1]) if d >= 3 else 1
         storage = torch.full((sz * planes,), float(fill), dtype=dtype, device=device)
         g = cls(storage, shape, h, lead, sy, sz)
         if halo_src is not None:
@@ -123,13 +143,15 @@ class Grid:
         return g
 
     @classmethod
-    def from_array(cls, arr, h: int, device="cuda", dtype=None):
+    def from_array(cls, arr, h, device="cuda", dtype=None):
         arr = np.asarray(arr)
         tdt = dtype or (torch.float64 if arr.dtype == np.float64 else torch.float32)
         return cls.allocate(arr.shape, h, tdt, device, halo_src=torch.from_numpy(np.ascontiguousarray(arr)))
 
     def empty_like(self, h=None):
-        return Grid.allocate(self.shape, self.h if h is None else h, self.dtype, self.storage.device)
+        if h is None:
+            h = self.h if self.symmetric else self.halo
+        return Grid.allocate(self.shape, h, self.dtype, self.storage.device)
 
     # ---- views ----
     @property
@@ -144,10 +166,11 @@ class Grid:
         return self.storage.as_strided(self.shape, self._strides(), self.storage.storage_offset() + self.offset)
 
     def padded(self) -> torch.Tensor:
-        h = self.h
-        shp = tuple(s + 2 * h for s in self.shape)
         d = self.ndim
-        off = self.offset - h - (h * self.sy if d >= 2 else 0) - (h * self.sz if d >= 3 else 0)
+        # numpy axis npax is paper axis d-1-npax
+        shp = tuple(self.shape[npax] + sum(self.halo[d - 1 - npax]) for npax in range(d))
+        lo = [p[0] for p in self.halo] + [0] * (3 - d)
+        off = self.offset - lo[0] - (lo[1] * self.sy if d >= 2 else 0) - (lo[2] * self.sz if d >= 3 else 0)
         return self.storage.as_strided(shp, self._strides(), self.storage.storage_offset() + off)
 
     def numpy(self) -> np.ndarray:
@@ -158,6 +181,10 @@ class Grid:
         g.ndim = self.ndim
         g.h = self.h
         g.dtype = _dtype_code(self.dtype)
+        if not self.symmetric:
+            g.halo_mode = 1
+            for a in range(self.ndim):
+                g.hlo[a], g.hhi[a] = self.halo[a]
         n = list(reversed(self.shape)) + [1] * (3 - self.ndim)
         for a in range(3):
             g.n[a] = n[a]

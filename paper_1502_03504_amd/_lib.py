@@ -27,10 +27,12 @@ class lope_grid(ctypes.Structure):
         ("ndim", ctypes.c_int32),
         ("h", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("halo_mode", ctypes.c_int32),
         ("n", ctypes.c_int64 * 3),
         ("stride", ctypes.c_int64 * 3),
         ("origin", ctypes.c_void_p),
+        ("hlo", ctypes.c_int32 * 3),
+        ("hhi", ctypes.c_int32 * 3),
     ]
 
 

@@ -38,12 +38,33 @@ int hip_fail(hipError_t e, const char* what) {
 size_t elem_size(int dtype) { return dtype == LOPE_F64 ? 8 : 4; }
 
 // ---- structural checks (no HIP calls) ----
+// Halo widths of axis a on the low (left/below) and high (right/above) side.
+int halo_lo(const lope_grid* g, int a) { return a >= g->ndim ? 0 : (g->halo_mode ? g->hlo[a] : g->h); }
+int halo_hi(const lope_grid* g, int a) { return a >= g->ndim ? 0 : (g->halo_mode ? g->hhi[a] : g->h); }
+bool has_halo(const lope_grid* g, int w) {
+    for (int a = 0; a < g->ndim; ++a)
+        if (halo_lo(g, a) < w || halo_hi(g, a) < w) return false;
+    return true;
+}
+
 int check_grid(const lope_grid* g, const char* name) {
     if (!g) return fail(LOPE_ERR_INVALID_ARG, "%s: null grid", name);
     if (g->ndim < 1 || g->ndim > 3) return fail(LOPE_ERR_INVALID_ARG, "%s: ndim %d not in 1..3", name, g->ndim);
     if (g->dtype != LOPE_F32 && g->dtype != LOPE_F64)
         return fail(LOPE_ERR_INVALID_ARG, "%s: unknown dtype %d", name, g->dtype);
-    if (g->h < 0 || g->h > (1 << 20)) return fail(LOPE_ERR_INVALID_ARG, "%s: bad halo width %d", name, g->h);
+    if (g->halo_mode != 0 && g->halo_mode != 1)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: halo_mode %d not 0 or 1", name, g->halo_mode);
+    if (g->halo_mode == 0 && (g->h < 0 || g->h > (1 << 20)))
+        return fail(LOPE_ERR_INVALID_ARG, "%s: bad halo width %d", name, g->h);
+    if (g->halo_mode == 1) {
+        for (int a = 0; a < 3; ++a) {
+            const bool used = a < g->ndim;
+            if (g->hlo[a] < 0 || g->hhi[a] < 0 || g->hlo[a] > (1 << 20) || g->hhi[a] > (1 << 20) ||
+                (!used && (g->hlo[a] || g->hhi[a])))
+                return fail(LOPE_ERR_INVALID_ARG, "%s: bad halo widths (%d, %d) on axis %d", name, g->hlo[a],
+                            g->hhi[a], a);
+        }
+    }
     for (int a = 0; a < 3; ++a) {
         if (a < g->ndim) {
             if (g->n[a] < 0 || g->n[a] > (int64_t)1 << 30)
@@ -53,11 +74,12 @@ int check_grid(const lope_grid* g, const char* name) {
         }
     }
     if (g->stride[0] != 1) return fail(LOPE_ERR_INVALID_ARG, "%s: stride[0] must be 1", name);
-    const int64_t h = g->h;
-    if (g->ndim >= 2 && g->stride[1] < g->n[0] + 2 * h)
-        return fail(LOPE_ERR_INVALID_ARG, "%s: stride[1]=%lld < n[0]+2h", name, (long long)g->stride[1]);
-    if (g->ndim >= 3 && g->stride[2] < g->stride[1] * (g->n[1] + 2 * h))
-        return fail(LOPE_ERR_INVALID_ARG, "%s: stride[2]=%lld < stride[1]*(n[1]+2h)", name, (long long)g->stride[2]);
+    const int64_t wx = halo_lo(g, 0) + halo_hi(g, 0), wy = halo_lo(g, 1) + halo_hi(g, 1);
+    if (g->ndim >= 2 && g->stride[1] < g->n[0] + wx)
+        return fail(LOPE_ERR_INVALID_ARG, "%s: stride[1]=%lld < n[0] plus the x halo", name, (long long)g->stride[1]);
+    if (g->ndim >= 3 && g->stride[2] < g->stride[1] * (g->n[1] + wy))
+        return fail(LOPE_ERR_INVALID_ARG, "%s: stride[2]=%lld < stride[1]*(n[1] plus the y halo)", name,
+                    (long long)g->stride[2]);
     if (!g->origin) return fail(LOPE_ERR_INVALID_ARG, "%s: null origin", name);
     return LOPE_OK;
 }
@@ -85,9 +107,8 @@ void span(const lope_grid* g, bool padded, uintptr_t* lo, uintptr_t* hi) {
     const int64_t es = (int64_t)elem_size(g->dtype);
     int64_t first = 0, last = 0;
     for (int a = 0; a < g->ndim; ++a) {
-        const int64_t w = padded ? g->h : 0;
-        first -= w * g->stride[a];
-        last += (g->n[a] - 1 + w) * g->stride[a];
+        first -= (padded ? halo_lo(g, a) : 0) * g->stride[a];
+        last += (g->n[a] - 1 + (padded ? halo_hi(g, a) : 0)) * g->stride[a];
     }
     *lo = (uintptr_t)((const char*)g->origin + first * es);
     *hi = (uintptr_t)((const char*)g->origin + (last + 1) * es);
@@ -115,6 +136,40 @@ int check_stencil(const lope_stencil* st, int ndim, int* ntaps_out) {
     if (nz > LOPE_MAX_TAPS)
         return fail(LOPE_ERR_UNSUPPORTED, "%d non-zero taps exceed the limit of %d", nz, LOPE_MAX_TAPS);
     if (ntaps_out) *ntaps_out = nz;
+    return LOPE_OK;
+}
+
+double round_to(double v, int dtype) { return dtype == LOPE_F32 ? (double)(float)v : v; }
+
+// The stencil's reach on each axis and side (section 3.5): the largest offset
+// toward lower (lo) / higher (hi) indices over the taps whose coefficient is
+// non-zero once rounded to `dtype`; with `reflect` the offsets are negated
+// (the adjoint reads x - o).  Then the check that a grid's halo covers it.
+void stencil_reach(const lope_stencil* st, int dtype, bool reflect, int lo[3], int hi[3]) {
+    const int r = st->radius, w = 2 * r + 1, d = st->ndim;
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = 0;
+    const int wy = d >= 2 ? w : 1, wz = d >= 3 ? w : 1;
+    for (int iz = 0; iz < wz; ++iz)
+        for (int iy = 0; iy < wy; ++iy)
+            for (int ix = 0; ix < w; ++ix) {
+                if (round_to(st->coeffs[ix + iy * w + iz * w * w], dtype) == 0.0) continue;
+                const int o[3] = {ix - r, d >= 2 ? iy - r : 0, d >= 3 ? iz - r : 0};
+                for (int a = 0; a < d; ++a) {
+                    const int oa = reflect ? -o[a] : o[a];
+                    if (-oa > lo[a]) lo[a] = -oa;
+                    if (oa > hi[a]) hi[a] = oa;
+                }
+            }
+}
+
+int check_reach(const lope_grid* g, const lope_stencil* st, bool reflect, const char* name) {
+    int lo[3], hi[3];
+    stencil_reach(st, g->dtype, reflect, lo, hi);
+    for (int a = 0; a < g->ndim; ++a)
+        if (lo[a] > halo_lo(g, a) || hi[a] > halo_hi(g, a))
+            return fail(LOPE_ERR_HALO_TOO_SMALL,
+                        "%s: the stencil reaches %d left / %d right on axis %d, the halo is %d / %d", name, lo[a],
+                        hi[a], a, halo_lo(g, a), halo_hi(g, a));
     return LOPE_OK;
 }
 
@@ -203,7 +258,6 @@ DevRule dev_rule(const lope_bc* bc, int ndim, bool zero_value) {
     return r;
 }
 
-double round_to(double v, int dtype) { return dtype == LOPE_F32 ? (double)(float)v : v; }
 
 // Build the job: coefficients rounded once to the grid dtype, taps in
 // lexicographic order, optionally reflected (adjoint: c'_o = c_{-o}).
@@ -404,9 +458,7 @@ int iterate_impl(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
         return rc;
     if (n_steps < 0) return fail(LOPE_ERR_INVALID_ARG, "n_steps %lld < 0", (long long)n_steps);
     if (tdepth < 0 || tdepth > 4) return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 0..4", tdepth);
-    if (st->radius > a->h || st->radius > b->h)
-        return fail(LOPE_ERR_HALO_TOO_SMALL, "stencil radius %d exceeds halo width (a.h=%d, b.h=%d)", st->radius,
-                    a->h, b->h);
+    if ((rc = check_reach(a, st, false, "a")) || (rc = check_reach(b, st, false, "b"))) return rc;
     if ((rc = check_alias(a, b, "a", "b"))) return rc;
     if (variant_req < LOPE_VARIANT_GENERIC || variant_req > (int)registry().v.size())
         return fail(LOPE_ERR_INVALID_ARG, "variant %d out of range", variant_req);
@@ -584,8 +636,13 @@ int lope_halo_fill(const lope_grid* g, const lope_bc* bc, void* stream) {
     if ((rc = check_grid(g, "grid")) || (rc = check_bc(bc, g->ndim))) return rc;
     if ((rc = device_ready())) return rc;
     if ((rc = check_memory(g, "grid"))) return rc;
-    if (is_empty(g) || g->h == 0) return LOPE_OK;
-    const hipError_t e = launch_halo_fill(dev_grid(g), g->ndim, g->h, g->dtype, dev_rule(bc, g->ndim, false),
+    if (is_empty(g)) return LOPE_OK;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = halo_lo(g, a);
+        hi[a] = halo_hi(g, a);
+    }
+    const hipError_t e = launch_halo_fill(dev_grid(g), lo, hi, g->dtype, dev_rule(bc, g->ndim, false),
                                           (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "halo fill launch");
 }
@@ -697,8 +754,7 @@ int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_
         (rc = check_same(ybar, xbar, "ybar", "xbar")) || (rc = check_bc(bc, ybar->ndim)) ||
         (rc = check_stencil(st, ybar->ndim, nullptr)))
         return rc;
-    if (st->radius > ybar->h)
-        return fail(LOPE_ERR_HALO_TOO_SMALL, "stencil radius %d exceeds halo width %d", st->radius, ybar->h);
+    if ((rc = check_reach(ybar, st, true, "ybar"))) return rc;
     if ((rc = check_alias(ybar, xbar, "ybar", "xbar"))) return rc;
     if ((rc = device_ready())) return rc;
     if ((rc = check_memory(ybar, "ybar")) || (rc = check_memory(xbar, "xbar"))) return rc;
@@ -736,7 +792,8 @@ int lope_apply_var(const lope_grid* src, const lope_grid* dst, const lope_varcoe
     for (int a = 0; a < 3; ++a)
         if (bc->kind[a] != LOPE_BC_PERIODIC)
             return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion supports periodic boundaries only");
-    if (src->h < 1 || vc->kappa->h < 1) return fail(LOPE_ERR_HALO_TOO_SMALL, "src and kappa need h >= 1");
+    if (!has_halo(src, 1) || !has_halo(vc->kappa, 1))
+        return fail(LOPE_ERR_HALO_TOO_SMALL, "src and kappa need a halo of 1 on every side");
     if ((rc = check_alias(src, dst, "src", "dst")) || (rc = check_alias(vc->kappa, dst, "kappa", "dst"))) return rc;
     if ((rc = device_ready())) return rc;
     if ((rc = check_memory(src, "src")) || (rc = check_memory(dst, "dst")) || (rc = check_memory(vc->kappa, "kappa")))
@@ -763,8 +820,8 @@ int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, cons
     for (int a = 0; a < 3; ++a)
         if (bc->kind[a] != LOPE_BC_PERIODIC)
             return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion supports periodic boundaries only");
-    if (lam_next->h < 1 || u_t->h < 1 || vc->kappa->h < 1)
-        return fail(LOPE_ERR_HALO_TOO_SMALL, "lam_next, u_t and kappa need h >= 1");
+    if (!has_halo(lam_next, 1) || !has_halo(u_t, 1) || !has_halo(vc->kappa, 1))
+        return fail(LOPE_ERR_HALO_TOO_SMALL, "lam_next, u_t and kappa need a halo of 1 on every side");
     if ((rc = check_alias(lam_next, lam, "lam_next", "lam")) || (rc = check_alias(u_t, lam, "u_t", "lam")) ||
         (rc = check_alias(vc->kappa, lam, "kappa", "lam")) || (rc = check_alias(gkappa, lam, "gkappa", "lam")) ||
         (rc = check_alias(gkappa, lam_next, "gkappa", "lam_next")) || (rc = check_alias(gkappa, u_t, "gkappa", "u_t")) ||
@@ -800,8 +857,8 @@ int lope_apply_var_adjoint2(const lope_grid* lam_next, const lope_grid* lam, con
     for (int a = 0; a < 3; ++a)
         if (bc->kind[a] != LOPE_BC_PERIODIC)
             return fail(LOPE_ERR_UNSUPPORTED, "variable-coefficient diffusion supports periodic boundaries only");
-    if (lam_next->h < 1 || u_t->h < 1 || u_tm1->h < 1 || vc->kappa->h < 1)
-        return fail(LOPE_ERR_HALO_TOO_SMALL, "lam_next, u_t, u_tm1 and kappa need h >= 1");
+    if (!has_halo(lam_next, 1) || !has_halo(u_t, 1) || !has_halo(u_tm1, 1) || !has_halo(vc->kappa, 1))
+        return fail(LOPE_ERR_HALO_TOO_SMALL, "lam_next, u_t, u_tm1 and kappa need a halo of 1 on every side");
     const lope_grid* ins[4] = {lam_next, u_t, u_tm1, vc->kappa};
     const char* names[4] = {"lam_next", "u_t", "u_tm1", "kappa"};
     for (int i = 0; i < 4; ++i)
@@ -855,7 +912,8 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         if (it.src.ndim != 2) return fail(LOPE_ERR_UNSUPPORTED, "%s: batches hold 2D grids", a);
         if (it.src.dtype != dtype) return fail(LOPE_ERR_INVALID_ARG, "%s: all grids of a batch share one dtype", a);
         if (it.stencil.radius > 1) return fail(LOPE_ERR_UNSUPPORTED, "%s: batch stencils have radius <= 1", a);
-        if (it.src.h < 1 || it.dst.h < 1) return fail(LOPE_ERR_HALO_TOO_SMALL, "%s: batch grids need h >= 1", a);
+        if ((rc = check_reach(&it.src, &it.stencil, false, a)) || (rc = check_reach(&it.dst, &it.stencil, false, b)))
+            return rc;
         if ((rc = check_alias(&it.src, &it.dst, a, b))) return rc;
     }
     if ((rc = device_ready())) return rc;

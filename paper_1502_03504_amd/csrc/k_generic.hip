@@ -47,24 +47,32 @@ k_generic(DevGrid src, DevGrid dst, DevRule rule, TapList<T> taps) {
 }
 
 // One workgroup per padded row (y, z); writes only the halo cells of the row.
+// One workgroup per padded row (y, z), halo widths lo/hi per axis: rows
+// inside the interior fill their left and right halo cells, the others the
+// whole padded row.
+struct HaloWidths {
+    int lo[3], hi[3];
+};
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_halo_fill(DevGrid g, DevRule rule, int hx, int hy, int hz) {
+k_halo_fill(DevGrid g, DevRule rule, HaloWidths w) {
     T* __restrict__ p = (T*)g.origin;
-    const int wy = g.ny + 2 * hy;
+    const int wy = g.ny + w.lo[1] + w.hi[1];
     const int row = blockIdx.x;
-    const int py = row % wy - hy;
-    const int pz = row / wy - hz;
+    const int py = row % wy - w.lo[1];
+    const int pz = row / wy - w.lo[2];
     const bool interior_row = py >= 0 && py < g.ny && pz >= 0 && pz < g.nz;
     const int64_t base = (int64_t)py * g.sy + (int64_t)pz * g.sz;
+    const int hx = w.lo[0] + w.hi[0];
     if (interior_row) {
-        for (int t = threadIdx.x; t < 2 * hx; t += kThreads) {
-            const int px = t < hx ? t - hx : g.nx + (t - hx);
+        for (int t = threadIdx.x; t < hx; t += kThreads) {
+            const int px = t < w.lo[0] ? t - w.lo[0] : g.nx + (t - w.lo[0]);
             p[base + px] = rule_load(p, g, rule, px, py, pz);
         }
     } else {
-        for (int t = threadIdx.x; t < g.nx + 2 * hx; t += kThreads) {
-            const int px = t - hx;
+        for (int t = threadIdx.x; t < g.nx + hx; t += kThreads) {
+            const int px = t - w.lo[0];
             p[base + px] = rule_load(p, g, rule, px, py, pz);
         }
     }
@@ -160,17 +168,21 @@ hipError_t launch_generic(const SweepJob& j, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_halo_fill(const DevGrid& g, int ndim, int h, int dtype, const DevRule& rule,
+hipError_t launch_halo_fill(const DevGrid& g, const int lo[3], const int hi[3], int dtype, const DevRule& rule,
                             hipStream_t s) {
-    const int hy = ndim >= 2 ? h : 0, hz = ndim >= 3 ? h : 0;
-    const int64_t rows = (int64_t)(g.ny + 2 * hy) * (g.nz + 2 * hz);
-    if (rows <= 0 || h == 0) return hipSuccess;
+    HaloWidths w;
+    int any = 0;
+    for (int a = 0; a < 3; ++a) {
+        w.lo[a] = lo[a];
+        w.hi[a] = hi[a];
+        any |= lo[a] | hi[a];
+    }
+    const int64_t rows = (int64_t)(g.ny + lo[1] + hi[1]) * (g.nz + lo[2] + hi[2]);
+    if (rows <= 0 || !any) return hipSuccess;
     if (dtype == LOPE_F32)
-        hipLaunchKernelGGL(k_halo_fill<float>, dim3((unsigned)rows), dim3(kThreads), 0, s, g, rule,
-                           h, hy, hz);
+        hipLaunchKernelGGL(k_halo_fill<float>, dim3((unsigned)rows), dim3(kThreads), 0, s, g, rule, w);
     else
-        hipLaunchKernelGGL(k_halo_fill<double>, dim3((unsigned)rows), dim3(kThreads), 0, s, g, rule,
-                           h, hy, hz);
+        hipLaunchKernelGGL(k_halo_fill<double>, dim3((unsigned)rows), dim3(kThreads), 0, s, g, rule, w);
     return hipGetLastError();
 }
 

@@ -52,7 +52,8 @@ struct SweepJob {
 
 // ---- launchers (return hipSuccess or the launch error) ----
 hipError_t launch_generic(const SweepJob& j, hipStream_t s);
-hipError_t launch_halo_fill(const DevGrid& g, int ndim, int h, int dtype, const DevRule& rule,
+// Fill the halo cells of g: lo[a] / hi[a] cells on the low / high side of axis a.
+hipError_t launch_halo_fill(const DevGrid& g, const int lo[3], const int hi[3], int dtype, const DevRule& rule,
                             hipStream_t s);
 hipError_t launch_accumulate(const DevGrid& part, int part_dtype, const DevGrid& total,
                              hipStream_t s);

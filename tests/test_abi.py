@@ -265,6 +265,78 @@ def test_grid_views_match_descriptor():
         P.Grid(torch.zeros(100), (8, 9, 10), 1, 1, 12, 132)
 
 
+def test_asymmetric_halo_views_and_descriptor():
+    """Per-axis (left, right) halos: the padded view, the interior view and
+    the descriptor agree, and the padded box holds exactly the widths."""
+    import torch
+    import paper_1502_03504_amd as P
+    halo = [(2, 0), (0, 1), (1, 3)]            # x, y, z
+    g = P.Grid.allocate((4, 5, 6), halo, torch.float32, "cpu")
+    d = g.descriptor()
+    assert d.halo_mode == 1 and list(d.hlo) == [2, 0, 1] and list(d.hhi) == [0, 1, 3]
+    assert g.padded().shape == (4 + 4, 5 + 1, 6 + 2)
+    assert g.interior().data_ptr() == d.origin
+    assert (d.origin - g.storage.data_ptr()) % 128 == 0
+    pad = g.padded()
+    pad.copy_(torch.arange(pad.numel(), dtype=torch.float32).reshape(pad.shape))
+    assert torch.equal(g.interior(), pad[1:5, 0:5, 2:8])
+    e = g.empty_like()
+    assert e.halo == g.halo and not e.symmetric
+    with pytest.raises(ValueError):
+        P.Grid.allocate((4, 5), [(1, -1), (0, 0)], torch.float32, "cpu")
+
+
+def test_asymmetric_halo_validation():
+    """The halo must cover the stencil's reach on each side; a one-sided
+    stencil needs a halo on that side only; the adjoint reaches the other way."""
+    E, H = _lib.LOPE_ERR_INVALID_ARG, _lib.LOPE_ERR_HALO_TOO_SMALL
+    NODEV = _lib.LOPE_ERR_NO_DEVICE
+
+    def agrid(lo, hi, origin=0x100000, n=(8, 8, 1), ndim=2):
+        g = grid(n=n, h=0, ndim=ndim, origin=origin, sy=n[0] + lo[0] + hi[0] + 4)
+        g.halo_mode = 1
+        for a in range(3):
+            g.hlo[a], g.hhi[a] = lo[a], hi[a]
+        return g
+
+    arr = np.zeros(9)
+    arr[3] = 1.0                                  # tap at ox = -1, oy = 0 (upwind)
+    s = _lib.lope_stencil()
+    s.ndim, s.radius = 2, 1
+    s.coeffs = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    left = agrid((1, 0, 0), (0, 0, 0))
+    right = agrid((0, 0, 0), (1, 0, 0))
+    assert apply(left, agrid((1, 0, 0), (0, 0, 0), origin=far()), s, bc()) == NODEV
+    assert apply(right, agrid((1, 0, 0), (0, 0, 0), origin=far()), s, bc()) == H
+    assert b"reaches" in L.lope_last_error()
+    adj = lambda y: L.lope_apply_adjoint(ctypes.byref(y), ctypes.byref(agrid((0, 0, 0), (0, 0, 0), origin=far())),
+                                         ctypes.byref(s), ctypes.byref(bc()), None, None)
+    assert adj(left) == H                         # the reflected tap reads to the right
+    assert adj(right) == NODEV
+    # coefficients count once rounded: 1e-50 vanishes in float32, not in float64
+    arr2 = np.zeros(9)
+    arr2[4], arr2[5] = 1.0, 1e-50
+    s2 = _lib.lope_stencil()
+    s2.ndim, s2.radius = 2, 1
+    s2.coeffs = arr2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    none = agrid((0, 0, 0), (0, 0, 0))
+    assert apply(none, agrid((0, 0, 0), (0, 0, 0), origin=far()), s2, bc()) == NODEV
+    none64 = agrid((0, 0, 0), (0, 0, 0))
+    none64.dtype = _lib.LOPE_F64
+    other64 = agrid((0, 0, 0), (0, 0, 0), origin=far())
+    other64.dtype = _lib.LOPE_F64
+    assert apply(none64, other64, s2, bc()) == H
+    # malformed widths
+    bad = agrid((1, 0, 0), (0, 0, 0))
+    bad.halo_mode = 2
+    assert apply(bad, agrid((1, 0, 0), (0, 0, 0), origin=far()), s, bc()) == E
+    assert apply(agrid((-1, 0, 0), (0, 0, 0)), agrid((1, 0, 0), (0, 0, 0), origin=far()), s, bc()) == E
+    assert apply(agrid((1, 0, 1), (0, 0, 0)), agrid((1, 0, 0), (0, 0, 0), origin=far()), s, bc()) == E  # unused z
+    tight = agrid((1, 0, 0), (2, 0, 0))
+    tight.stride[1] = 8 + 2                       # < n[0] + 1 + 2
+    assert apply(tight, agrid((1, 0, 0), (0, 0, 0), origin=far()), s, bc()) == E
+
+
 def test_committed_tuning_table_registers_completely():
     import json
     from paper_1502_03504_amd import tune
