@@ -11,7 +11,7 @@ for a reader to check against the paper by eye, in float64 arithmetic with the
 state rounded to the grid dtype after every sweep:
 
 * ``stencil``   — halo widths (symmetric or per-axis left/right), halo rule,
-  stencil reach, sweep, iteration (fixed count or until a
+  stencil reach, sweep, iteration, two-stage steps (fixed count or until a
   convergence test holds), windowed sampling, adjoint;
 * ``diffusion`` — the variable-coefficient diffusion step and its gradient.
 
@@ -21,7 +21,7 @@ closed forms, invariants, library spectral routines or brute force; none is
 """
 from .stencil import (  # noqa: F401
     rule_extend, halo_widths, halo_fill, stencil_reach, sweep, iterate, iterate_until, sweep_at, adjoint,
-    result_index,
+    result_index, stages_step, stages_iterate,
 )
 from .diffusion import (  # noqa: F401
     diffusion_step, diffusion_forward, diffusion_loss, diffusion_gradient,

@@ -205,6 +205,46 @@ def iterate_until(u0: np.ndarray, coeffs: np.ndarray, kinds, g: float, max_steps
     return u, int(max_steps), res
 
 
+def stages_step(u: np.ndarray, c1: np.ndarray, c2: np.ndarray, alpha: float, kinds, g: float) -> np.ndarray:
+    """One step of two local-element functions applied in sequence, with a
+    share of the starting state (two-stage schemes such as RK2/Heun; the
+    paper leaves fusing small functions to the compiler, section 3.5, and
+    notes that intermediate results of multi-step updates are not stored
+    automatically, section 5):
+
+        v  = S1(B(u))            the first function's result, a state of the
+                                 grid's dtype whose halo follows the same rule;
+        u' = alpha * u + S2(B(v))
+
+    The second sum is taken in float64 with alpha and the coefficients rounded
+    once to the grid dtype, and rounded to the dtype once.  With alpha = 0 the
+    step is the composition of the two sweeps.
+    """
+    v = sweep(u, c1, kinds, g)
+    if u.size == 0:
+        return v
+    r2 = _radius(c2)
+    if c2.ndim != u.ndim:
+        raise ValueError("stencil and field dimension differ")
+    gd = float(np.asarray(g, dtype=u.dtype))
+    ext = rule_extend(v, r2, kinds, gd)
+    a = float(np.asarray(alpha, dtype=u.dtype))
+    y = a * u.astype(np.float64)
+    for off, c in _taps(c2, u.dtype):
+        sl = tuple(slice(r2 + o, r2 + o + n) for o, n in zip(off, u.shape))
+        y += c * ext[sl]
+    return y.astype(u.dtype)
+
+
+def stages_iterate(u0: np.ndarray, c1: np.ndarray, c2: np.ndarray, alpha: float, kinds, g: float,
+                   n_steps: int) -> np.ndarray:
+    """n_steps two-stage steps, each reading only the previous state."""
+    u = np.array(u0, copy=True)
+    for _ in range(int(n_steps)):
+        u = stages_step(u, c1, c2, alpha, kinds, g)
+    return u
+
+
 def result_index(n_steps: int) -> int:
     """Which of the two ping-pong buffers holds the state after n_steps sweeps."""
     return int(n_steps) % 2
