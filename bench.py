@@ -251,6 +251,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-grids measurement")
     ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size sweep workloads")
     ap.add_argument("--no-converge", action="store_true", help="skip the convergence-checked iteration")
+    ap.add_argument("--no-stages", action="store_true", help="skip the two-stage (Heun) steps")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -331,6 +332,30 @@ def main():
                                                   "vs_plain": round(pts * done / el / 1e9 / value, 3)}
         log("converge:", converge)
 
+    stages = None
+    if not args.no_stages:
+        # Heun's method for the same heat problem: v = S u, u' = u/2 + (S/2) v,
+        # one fused pass per step, against the same two sweeps as two launches
+        half = synth.Stencil(3, 1, 0.5 * st.coeffs)
+        nst = 200
+        L.lope_iterate_stages(a, b, st, half, 0.5, bc, 2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        L.lope_iterate_stages(a, b, st, half, 0.5, bc, nst)
+        e1.record(stream)
+        e1.synchronize()
+        ms_f = e0.elapsed_time(e1)
+        e0.record(stream)
+        for _ in range(nst):
+            L.lope_iterate(a, b, st, bc, 2, tdepth=1)
+        e1.record(stream)
+        e1.synchronize()
+        ms_u = e0.elapsed_time(e1)
+        stages = {"workload": "heun_7pt_%d^3_f32_periodic_%d_steps" % (n, nst), "ms": round(ms_f, 3),
+                  "GPts_steps": round(pts * nst / (ms_f * 1e-3) / 1e9, 1),
+                  "two_sweeps_ms": round(ms_u, 3), "speedup_vs_two_sweeps": round(ms_u / ms_f, 2)}
+        log("stages:", stages)
+
     adjoint = None
     if not args.no_adjoint:
         del a, b
@@ -381,6 +406,7 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(info.split()[0], n, sweeps)},
         "cpu_baseline": cpu,
         "converge": converge,
+        "stages": stages,
         "adjoint_forward": adjoint,
         "batch": batch,
         "copy_reference": copy_ref,

@@ -227,6 +227,38 @@ int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stenci
 int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_stencil* st,
                        const lope_bc* bc, double* gbar_dirichlet, void* stream);
 
+/* ---- two local-element functions per step ------------------------------- */
+
+/* Two local-element functions applied in sequence with a share of the
+ * starting state: two-stage schemes such as Heun's method or the midpoint
+ * rule, fused in one pass over memory (the paper leaves fusing small
+ * functions to the compiler, section 3.5, and notes that intermediate results
+ * of multi-step updates are not stored automatically, section 5):
+ *   v  = S1(B(u))                a state of the grid type, never stored;
+ *   u' = alpha * u + S2(B(v))    B gives v's halo by the same rule.
+ * Per point, v is evaluated exactly as lope_apply would; the second sum is
+ * alpha*u (when alpha != 0) followed by fmas over S2's non-zero taps in
+ * lexicographic order, so with alpha == 0 a step equals two lope_apply calls
+ * value for value.  Both stencils have the grid's ndim and at most 64
+ * non-zero taps (else LOPE_ERR_UNSUPPORTED). */
+typedef struct lope_stages {
+    const lope_stencil* first;    /* S1 */
+    const lope_stencil* second;   /* S2 */
+    double alpha;                 /* rounded once to the grid dtype */
+} lope_stages;
+
+/* One two-stage step from src to dst.  src's halo must cover the first
+ * stencil's reach (the intermediate's halo comes from the rule); otherwise
+ * as lope_apply. */
+int lope_apply_stages(const lope_grid* src, const lope_grid* dst, const lope_stages* sg,
+                      const lope_bc* bc, void* stream);
+
+/* n_steps two-stage steps alternating between a and b, one pass over memory
+ * per step; *result_index = n_steps mod 2 (0: the state is in a).  Both grids'
+ * halos must cover the first stencil's reach.  result_index must not be NULL. */
+int lope_iterate_stages(const lope_grid* a, const lope_grid* b, const lope_stages* sg,
+                        const lope_bc* bc, int64_t n_steps, void* stream, int32_t* result_index);
+
 /* ---- variable-coefficient diffusion (3D, periodic) ------------------------ */
 
 /* dst = src + dt * div(kappa grad src) with arithmetic-mean faces (see

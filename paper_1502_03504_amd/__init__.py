@@ -22,7 +22,7 @@ from ._lib import LopeError, check, load
 
 __all__ = [
     "Grid", "LopeError", "lope_get_device", "lope_halo_fill", "lope_apply", "lope_iterate",
-    "lope_iterate_tuned", "lope_iterate_until", "lope_apply_adjoint", "lope_apply_var", "lope_apply_var_adjoint",
+    "lope_iterate_tuned", "lope_iterate_until", "lope_apply_stages", "lope_iterate_stages", "lope_apply_adjoint", "lope_apply_var", "lope_apply_var_adjoint",
     "lope_accumulate", "lope_variant_count", "lope_variant_info", "lope_select_variant",
     "lope_tune_set", "variants", "BatchPlan", "lope_batch_plan_create", "lope_batch_apply",
     "lope_batch_apply_per_grid", "lope_batch_plan_destroy", "DIRICHLET", "PERIODIC",
@@ -295,6 +295,29 @@ def lope_iterate_until(a: Grid, b: Grid, stencil, bc, max_steps: int, check_ever
                                     int(check_every), float(tol), int(tdepth), ctypes.c_void_p(scratch.data_ptr()),
                                     _stream(stream), _ref(steps), _ref(res), _ref(idx)))
     return idx.value, steps.value, res.value
+
+
+def _stages(first, second, alpha):
+    s1, s2 = _Stencil(first), _Stencil(second)
+    sg = _lib.lope_stages(ctypes.pointer(s1.c), ctypes.pointer(s2.c), float(alpha))
+    return sg, (s1, s2)
+
+
+def lope_apply_stages(src: Grid, dst: Grid, first, second, alpha: float, bc, stream=None) -> None:
+    """One two-stage step: dst = alpha*src + S2(B(S1(B(src))))."""
+    sg, keep = _stages(first, second, alpha)
+    check(load().lope_apply_stages(_ref(src.descriptor()), _ref(dst.descriptor()), _ref(sg),
+                                   _ref(_bc(bc, src.ndim)), _stream(stream)))
+
+
+def lope_iterate_stages(a: Grid, b: Grid, first, second, alpha: float, bc, n_steps: int, stream=None) -> int:
+    """n_steps two-stage steps alternating between a and b; returns 0 if the
+    final state is in a, 1 if in b."""
+    sg, keep = _stages(first, second, alpha)
+    idx = ctypes.c_int32(-1)
+    check(load().lope_iterate_stages(_ref(a.descriptor()), _ref(b.descriptor()), _ref(sg), _ref(_bc(bc, a.ndim)),
+                                     int(n_steps), _stream(stream), _ref(idx)))
+    return idx.value
 
 
 def lope_apply_adjoint(ybar: Grid, xbar: Grid, stencil, bc, gbar: torch.Tensor = None, stream=None) -> None:

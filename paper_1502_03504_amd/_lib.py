@@ -68,6 +68,14 @@ class lope_tuning(ctypes.Structure):
     ]
 
 
+class lope_stages(ctypes.Structure):
+    _fields_ = [
+        ("first", ctypes.POINTER(lope_stencil)),
+        ("second", ctypes.POINTER(lope_stencil)),
+        ("alpha", ctypes.c_double),
+    ]
+
+
 class lope_batch_item(ctypes.Structure):
     _fields_ = [
         ("src", lope_grid),
@@ -101,6 +109,9 @@ SIGNATURES = {
     "lope_apply_var_adjoint2": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_grid), P(lope_grid),
                                                P(lope_varcoef), P(lope_bc), P(lope_grid), c_void_p]),
     "lope_accumulate": (ctypes.c_int, [P(lope_grid), P(lope_grid), c_void_p]),
+    "lope_apply_stages": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stages), P(lope_bc), c_void_p]),
+    "lope_iterate_stages": (ctypes.c_int, [P(lope_grid), P(lope_grid), P(lope_stages), P(lope_bc), ctypes.c_int64,
+                                           c_void_p, P(ctypes.c_int32)]),
     "lope_batch_plan_create": (ctypes.c_int, [P(lope_batch_item), ctypes.c_int64, ctypes.c_int64, c_void_p,
                                               P(c_void_p)]),
     "lope_batch_apply": (ctypes.c_int, [c_void_p, c_void_p]),

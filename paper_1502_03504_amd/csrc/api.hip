@@ -740,6 +740,73 @@ int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stenci
     return LOPE_OK;
 }
 
+namespace {
+
+// Two-stage steps: validation, then one pass per step with a fused two-level
+// variant (the tuned depth-2 choice for the first stencil if it can also take
+// the second, else the first that can) or the one-thread-per-point kernel.
+int stages_impl(const lope_grid* a, const lope_grid* b, const lope_stages* sg, const lope_bc* bc, int64_t n_steps,
+                void* stream, int32_t* result_index) {
+    if (!result_index) return fail(LOPE_ERR_INVALID_ARG, "null result_index");
+    *result_index = 0;
+    if (!sg || !sg->first || !sg->second) return fail(LOPE_ERR_INVALID_ARG, "null stages or stencil");
+    int rc;
+    if ((rc = check_grid(a, "a")) || (rc = check_grid(b, "b")) || (rc = check_same(a, b, "a", "b")) ||
+        (rc = check_bc(bc, a->ndim)) || (rc = check_stencil(sg->first, a->ndim, nullptr)) ||
+        (rc = check_stencil(sg->second, a->ndim, nullptr)))
+        return rc;
+    if (n_steps < 0) return fail(LOPE_ERR_INVALID_ARG, "n_steps %lld < 0", (long long)n_steps);
+    if ((rc = check_reach(a, sg->first, false, "a")) || (rc = check_reach(b, sg->first, false, "b"))) return rc;
+    if ((rc = check_alias(a, b, "a", "b"))) return rc;
+    static thread_local StageJob sj;
+    build_job(sj.s1, a, b, sg->first, bc, false);
+    build_job(sj.s2, a, b, sg->second, bc, false);
+    if (sj.s1.ntaps > kStageTaps || sj.s2.ntaps > kStageTaps)
+        return fail(LOPE_ERR_UNSUPPORTED, "two-stage steps take stencils of at most %d non-zero taps", kStageTaps);
+    sj.alpha = round_to(sg->alpha, a->dtype);
+    if ((rc = device_ready())) return rc;
+    if ((rc = check_memory(a, "a")) || (rc = check_memory(b, "b"))) return rc;
+    if (is_empty(a) || n_steps == 0) return LOPE_OK;
+    auto& R = registry().v;
+    auto takes = [&](int v) {
+        return v > 0 && R[v - 1].sfn && variant_fits(R[v - 1], sj.s1, 2) && variant_fits(R[v - 1], sj.s2, 2);
+    };
+    int chunk = 0, variant = 0;
+    {
+        const Plan p = choose(sj.s1, 2, 0, 0);
+        if (p.tdepth == 2 && takes(p.variant)) {
+            variant = p.variant;
+            chunk = p.chunk;
+        }
+    }
+    for (size_t i = 0; !variant && i < R.size(); ++i)
+        if (takes((int)i + 1)) variant = (int)i + 1;
+    const DevGrid ga = dev_grid(a), gb = dev_grid(b);
+    const hipStream_t s = (hipStream_t)stream;
+    for (int64_t t = 0; t < n_steps; ++t) {
+        sj.s1.src = (t & 1) ? gb : ga;
+        sj.s1.dst = (t & 1) ? ga : gb;
+        const hipError_t e = variant ? R[variant - 1].sfn(sj, chunk > 0 ? chunk : R[variant - 1].default_chunk, s)
+                                     : launch_stages_generic(sj, s);
+        if (e != hipSuccess) return hip_fail(e, "two-stage launch");
+    }
+    *result_index = (int32_t)(n_steps & 1);
+    return LOPE_OK;
+}
+
+}  // namespace
+
+int lope_apply_stages(const lope_grid* src, const lope_grid* dst, const lope_stages* sg, const lope_bc* bc,
+                      void* stream) {
+    int32_t idx = 0;
+    return stages_impl(src, dst, sg, bc, 1, stream, &idx);
+}
+
+int lope_iterate_stages(const lope_grid* a, const lope_grid* b, const lope_stages* sg, const lope_bc* bc,
+                        int64_t n_steps, void* stream, int32_t* result_index) {
+    return stages_impl(a, b, sg, bc, n_steps, stream, result_index);
+}
+
 int lope_iterate_tuned(const lope_grid* a, const lope_grid* b, const lope_stencil* st, const lope_bc* bc,
                        int64_t n_steps, const lope_tuning* tune, void* stream, int32_t* result_index) {
     if (!tune) return fail(LOPE_ERR_INVALID_ARG, "null tuning");

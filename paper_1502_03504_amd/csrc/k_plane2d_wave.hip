@@ -7,27 +7,30 @@
 namespace lope {
 namespace {
 
-template <typename T, int TD, bool BOX, int NW, bool DX, bool DY, bool RES>
+template <typename T, int TD, bool BOX, int NW, bool DX, bool DY, bool RES, int STG>
 __global__ void __launch_bounds__(NW * 64)
-k_plane2d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef9<T> cf, int chunk, int strips, int nwaves,
-               int nblocks_padded, double* residual) {
+k_plane2d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef9<T> cf, Coef9<T> cf2, T alpha, int chunk, int strips,
+               int nwaves, int nblocks_padded, double* residual) {
     // the wave index is uniform across the wave: say so, so that rows, loop
     // bounds and the row rule stay scalar
     const int wave = xcd_logical_block(nblocks_padded) * NW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (wave >= nwaves) return;   // whole waves leave; the kernel has no barrier
     const int tx = wave % strips, ty = wave / strips;
     const int y0 = ty * chunk;
-    plane2d_wave_strip<T, TD, BOX, DX, DY, RES>(src, dst, (T)rule.g, cf.c, tx * (64 - 2 * TD), y0,
-                                                min(y0 + chunk, src.ny), residual);
+    plane2d_wave_strip<T, TD, BOX, DX, DY, RES, STG>(src, dst, (T)rule.g, cf.c, tx * (64 - 2 * TD), y0,
+                                                     min(y0 + chunk, src.ny), residual, cf2.c, alpha);
 }
 
-template <typename T, int TD, bool BOX, int NW>
-hipError_t run_plane2d_wave(const SweepJob& j, int chunk, hipStream_t s) {
+template <typename T>
+Coef9<T> coef9(const SweepJob& j) {
     Coef9<T> cf;
-    for (int oy = -1; oy <= 1; ++oy)
-        for (int ox = -1; ox <= 1; ++ox) {
-            cf.c[(ox + 1) + 3 * (oy + 1)] = (T)j.dense[(ox + 1) + (oy + 1) * 3];
-        }
+    for (int t = 0; t < 9; ++t) cf.c[t] = (T)j.dense[t];   // (ox + 1) + 3 * (oy + 1)
+    return cf;
+}
+
+template <typename T, int TD, bool BOX, int NW, int STG>
+hipError_t launch_wave(const SweepJob& j, const Coef9<T>& cf, const Coef9<T>& cf2, T alpha, int chunk,
+                       hipStream_t s) {
     if (chunk <= 0) chunk = 128;
     const int out_cols = 64 - 2 * TD;
     const int strips = (j.src.nx + out_cols - 1) / out_cols;
@@ -38,9 +41,9 @@ hipError_t run_plane2d_wave(const SweepJob& j, int chunk, hipStream_t s) {
     const int nb = (nw + NW - 1) / NW;
     const int nbp = padded_block_count(nb);
     const bool dx = !j.rule.per[0], dy = !j.rule.per[1];
-#define LOPE_WAVE_LAUNCH(A, B, C)                                                                                 \
-    hipLaunchKernelGGL((k_plane2d_wave<T, TD, BOX, NW, A, B, C>), dim3(nbp), dim3(NW * 64), 0, s, j.src, j.dst, \
-                       j.rule, cf, chunk, strips, nw, nbp, j.residual)
+#define LOPE_WAVE_LAUNCH(A, B, C)                                                                                  \
+    hipLaunchKernelGGL((k_plane2d_wave<T, TD, BOX, NW, A, B, C, STG>), dim3(nbp), dim3(NW * 64), 0, s, j.src,     \
+                       j.dst, j.rule, cf, cf2, alpha, chunk, strips, nw, nbp, j.residual)
 #define LOPE_WAVE_RULE(C)                  \
     if (dx && dy)                          \
         LOPE_WAVE_LAUNCH(true, true, C);   \
@@ -50,8 +53,8 @@ hipError_t run_plane2d_wave(const SweepJob& j, int chunk, hipStream_t s) {
         LOPE_WAVE_LAUNCH(false, true, C);  \
     else                                   \
         LOPE_WAVE_LAUNCH(false, false, C)
-    if (j.residual) {
-        LOPE_WAVE_RULE(true);
+    if (STG == 0 && j.residual) {
+        LOPE_WAVE_RULE(STG == 0);
     } else {
         LOPE_WAVE_RULE(false);
     }
@@ -60,9 +63,28 @@ hipError_t run_plane2d_wave(const SweepJob& j, int chunk, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T, int TD, bool BOX, int NW>
+hipError_t run_plane2d_wave(const SweepJob& j, int chunk, hipStream_t s) {
+    const Coef9<T> cf = coef9<T>(j);
+    return launch_wave<T, TD, BOX, NW, 0>(j, cf, cf, (T)0, chunk, s);
+}
+
+// One two-stage step per pass (levels 1 and 2 with the two stencils).
+template <typename T, int TD, bool BOX, int NW>
+hipError_t run_plane2d_wave_stages(const StageJob& sj, int chunk, hipStream_t s) {
+    if constexpr (TD != 2) {
+        return hipErrorInvalidValue;
+    } else {
+        const Coef9<T> cf = coef9<T>(sj.s1), cf2 = coef9<T>(sj.s2);
+        if (sj.alpha != 0.0) return launch_wave<T, TD, BOX, NW, 2>(sj.s1, cf, cf2, (T)sj.alpha, chunk, s);
+        return launch_wave<T, TD, BOX, NW, 1>(sj.s1, cf, cf2, (T)0, chunk, s);
+    }
+}
+
 #define PWAVE(T, DT, TD, BOX, NW, CH)                                                                  \
     {"plane2dw_" #T "_r1_t" #TD "_nw" #NW "_" #BOX, FAM_PLANE2D, 2, 1, TD, DT, BOX, 64 - 2 * (TD), 0, \
-     (NW) * 64, CH, &run_plane2d_wave<T, TD, BOX, NW>, 1}
+     (NW) * 64, CH, &run_plane2d_wave<T, TD, BOX, NW>, 1,                                          \
+     (TD) == 2 ? &run_plane2d_wave_stages<T, TD, BOX, NW> : nullptr}
 
 const Variant kPlane2dWave[] = {
     PWAVE(float, LOPE_F32, 1, true, 4, 128),

@@ -86,10 +86,14 @@ __device__ __forceinline__ void unroll_steps(int j, int jend, F& f) {
     }
 }
 
-template <typename T, int R, int TD, int BX, int BY, int NT, bool DXY, bool RES>
+// STG: 0 = TD sweeps of one stencil; 1, 2 = one two-stage step (TD = 2):
+// level 1 applies cf, level 2 applies cf2 (plus alpha times the starting
+// state when STG = 2).
+template <typename T, int R, int TD, int BX, int BY, int NT, bool DXY, bool RES, int STG>
 __global__ void __launch_bounds__(NT, (FlatShape<T, R, TD, BX, BY, NT>::WAVES_PER_EU))
-k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chunk, int tiles_x, int tiles_y,
-              int nblocks, int nblocks_padded, double* residual) {
+k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, FlatCoef<T, R> cf2, T alpha, int chunk,
+              int tiles_x, int tiles_y, int nblocks, int nblocks_padded, double* residual) {
+    static_assert(STG == 0 || TD == 2, "a two-stage step is two levels");
     typedef FlatShape<T, R, TD, BX, BY, NT> S;
     constexpr int G = S::G, W = S::W, H = S::H, NPOS = S::NPOS, NP = S::NP, RING = S::RING;
     constexpr int GUARD = S::GUARD, PLANE = S::PLANE;
@@ -165,6 +169,9 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
     // One march step at ring phase PH: ring slot (s + PH) % RING holds the
     // plane at logical position s (0 = oldest) of every level's window.
     double rmax = 0.0;   // RES: max |last sweep - the sweep before| over this thread's outputs
+    // STG: the starting state at the point level 1 is computing, kept until
+    // level 2 reaches the same plane R+1 steps later
+    T dly[NP][RING];
     auto step = [&](int j, auto phase) {
         constexpr int PH = decltype(phase)::value;
         const int rb = (j & 1) ^ 1;
@@ -188,18 +195,24 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
             for (int i = 0; i < NP; ++i) {
                 const int p = tid + i * NT;
                 const T* rk = ring[k - 1][i];
-                T v = cf.c[0] * rk[(0 + PH) % RING];
+                const FlatCoef<T, R>& c = (STG && k == 2) ? cf2 : cf;
+                T v;
+                if (STG == 2 && k == 2)   // alpha * u, then every tap as an fma
+                    v = fma(c.c[0], rk[(0 + PH) % RING], alpha * dly[i][(PH + RING - (R + 1)) % RING]);
+                else
+                    v = c.c[0] * rk[(0 + PH) % RING];
+                if (STG && k == 1) dly[i][PH] = rk[(R + PH) % RING];
 #pragma unroll
-                for (int s = 1; s < R; ++s) v = fma(cf.c[s], rk[(s + PH) % RING], v);
+                for (int s = 1; s < R; ++s) v = fma(c.c[s], rk[(s + PH) % RING], v);
 #pragma unroll
-                for (int o = -R; o < 0; ++o) v = fma(cf.c[2 * R + o], L[p + o * W], v);
+                for (int o = -R; o < 0; ++o) v = fma(c.c[2 * R + o], L[p + o * W], v);
 #pragma unroll
                 for (int o = -R; o <= R; ++o)
-                    v = fma(cf.c[3 * R + o], o == 0 ? rk[(R + PH) % RING] : L[p + o], v);
+                    v = fma(c.c[3 * R + o], o == 0 ? rk[(R + PH) % RING] : L[p + o], v);
 #pragma unroll
-                for (int o = 1; o <= R; ++o) v = fma(cf.c[4 * R + o], L[p + o * W], v);
+                for (int o = 1; o <= R; ++o) v = fma(c.c[4 * R + o], L[p + o * W], v);
 #pragma unroll
-                for (int o = 1; o <= R; ++o) v = fma(cf.c[5 * R + o], rk[(R + o + PH) % RING], v);
+                for (int o = 1; o <= R; ++o) v = fma(c.c[5 * R + o], rk[(R + o + PH) % RING], v);
                 if (DXY) v = blend(live[i], v, g);
                 if (k == TD) {
                     if (keep[i] && zin) {
@@ -228,8 +241,8 @@ k_star3d_flat(DevGrid src, DevGrid dst, DevRule rule, FlatCoef<T, R> cf, int chu
     if (RES) residual_merge(rmax, residual);
 }
 
-template <typename T, int R, int TD, int BX, int BY, int NT>
-hipError_t run_star3d_flat(const SweepJob& j, int chunk, hipStream_t s) {
+template <typename T, int R>
+FlatCoef<T, R> flat_coef(const SweepJob& j) {
     FlatCoef<T, R> cf;
     const int r = j.radius;
     const int w = 2 * r + 1;
@@ -241,6 +254,12 @@ hipError_t run_star3d_flat(const SweepJob& j, int chunk, hipStream_t s) {
     for (int o = -R; o <= R; ++o) cf.c[3 * R + o] = dense(o, 0, 0);
     for (int o = 1; o <= R; ++o) cf.c[4 * R + o] = dense(0, o, 0);
     for (int o = 1; o <= R; ++o) cf.c[5 * R + o] = dense(0, 0, o);
+    return cf;
+}
+
+template <typename T, int R, int TD, int BX, int BY, int NT, int STG>
+hipError_t launch_flat(const SweepJob& j, const FlatCoef<T, R>& cf, const FlatCoef<T, R>& cf2, T alpha, int chunk,
+                       hipStream_t s) {
     if (chunk <= 0) chunk = 64;
     const int tiles_x = (j.src.nx + BX - 1) / BX;
     const int tiles_y = (j.src.ny + BY - 1) / BY;
@@ -250,14 +269,14 @@ hipError_t run_star3d_flat(const SweepJob& j, int chunk, hipStream_t s) {
     const int nb = (int)nb64;
     const int nbp = padded_block_count(nb);
     const bool dxy = !j.rule.per[0] || !j.rule.per[1];
-#define LOPE_FLAT_LAUNCH(A, B)                                                                                \
-    hipLaunchKernelGGL((k_star3d_flat<T, R, TD, BX, BY, NT, A, B>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, \
-                       j.rule, cf, chunk, tiles_x, tiles_y, nb, nbp, j.residual)
-    if (j.residual) {
+#define LOPE_FLAT_LAUNCH(A, B)                                                                                     \
+    hipLaunchKernelGGL((k_star3d_flat<T, R, TD, BX, BY, NT, A, B, STG>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, \
+                       j.rule, cf, cf2, alpha, chunk, tiles_x, tiles_y, nb, nbp, j.residual)
+    if (STG == 0 && j.residual) {
         if (dxy)
-            LOPE_FLAT_LAUNCH(true, true);
+            LOPE_FLAT_LAUNCH(true, STG == 0);
         else
-            LOPE_FLAT_LAUNCH(false, true);
+            LOPE_FLAT_LAUNCH(false, STG == 0);
     } else {
         if (dxy)
             LOPE_FLAT_LAUNCH(true, false);
@@ -268,9 +287,29 @@ hipError_t run_star3d_flat(const SweepJob& j, int chunk, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T, int R, int TD, int BX, int BY, int NT>
+hipError_t run_star3d_flat(const SweepJob& j, int chunk, hipStream_t s) {
+    const FlatCoef<T, R> cf = flat_coef<T, R>(j);
+    return launch_flat<T, R, TD, BX, BY, NT, 0>(j, cf, cf, (T)0, chunk, s);
+}
+
+// One two-stage step per pass (the two-level kernel with the second stencil
+// and alpha at level 2).
+template <typename T, int R, int TD, int BX, int BY, int NT>
+hipError_t run_star3d_flat_stages(const StageJob& sj, int chunk, hipStream_t s) {
+    if constexpr (TD != 2) {
+        return hipErrorInvalidValue;
+    } else {
+        const FlatCoef<T, R> cf = flat_coef<T, R>(sj.s1), cf2 = flat_coef<T, R>(sj.s2);
+        if (sj.alpha != 0.0) return launch_flat<T, R, TD, BX, BY, NT, 2>(sj.s1, cf, cf2, (T)sj.alpha, chunk, s);
+        return launch_flat<T, R, TD, BX, BY, NT, 1>(sj.s1, cf, cf2, (T)0, chunk, s);
+    }
+}
+
 #define FSTAR(T, DT, R, TD, BX, BY, NT, CH)                                                      \
     {"star3df_" #T "_r" #R "_t" #TD "_" #BX "x" #BY "_nt" #NT, FAM_STAR3D_FLAT, 3, R, TD, DT, 0, \
-     BX, BY, NT, CH, &run_star3d_flat<T, R, TD, BX, BY, NT>, 1}
+     BX, BY, NT, CH, &run_star3d_flat<T, R, TD, BX, BY, NT>, 1,                                  \
+     (TD) == 2 ? &run_star3d_flat_stages<T, R, TD, BX, BY, NT> : nullptr}
 
 const Variant kStar3dFlat[] = {
     FSTAR(float, LOPE_F32, 1, 3, 64, 32, 512, 128),

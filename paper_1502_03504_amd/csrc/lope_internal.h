@@ -68,6 +68,17 @@ enum Family { FAM_GENERIC = 0, FAM_STAR3D = 1, FAM_PLANE2D = 2, FAM_STAR3D_VEC =
 
 typedef hipError_t (*VariantFn)(const SweepJob& j, int chunk, hipStream_t s);
 
+// Two local-element functions per step: s1 holds the grids, the rule and the
+// first stencil; s2 the second stencil (its grids and rule are s1's).
+struct StageJob {
+    SweepJob s1, s2;
+    double alpha;   // rounded to the grid dtype
+};
+typedef hipError_t (*StageFn)(const StageJob& j, int chunk, hipStream_t s);
+// One thread per point, both stencils from tap lists (<= kStageTaps each).
+constexpr int kStageTaps = 64;
+hipError_t launch_stages_generic(const StageJob& j, hipStream_t s);
+
 struct Variant {
     const char* name;
     int family;
@@ -77,6 +88,7 @@ struct Variant {
     int default_chunk;
     VariantFn fn;
     int res;                        // 1: honours SweepJob::residual
+    StageFn sfn;                    // two-stage step in one pass (tdepth 2 kernels), or null
 };
 
 // Registries filled by each kernel file.

@@ -24,7 +24,9 @@
 // g at every level (a wave-uniform choice).
 //
 // With RES the strip also merges max |u_TD - u_(TD-1)| over its outputs (the
-// change made by its last sweep) into the device double `residual`.
+// change made by its last sweep) into the device double `residual`.  With
+// STG (TD = 2) it makes one two-stage step: level 1 applies c9, level 2 the
+// second table c9b plus alpha times the starting state (STG = 2).
 //
 // Every argument must be uniform across the wave, and all 64 lanes must be
 // active (the DPP shifts read every lane).
@@ -84,9 +86,11 @@ __device__ __forceinline__ void wave_steps(int j, int jend, F& f) {
     }
 }
 
-template <typename T, int TD, bool BOX, bool DX, bool DY, bool RES = false>
+template <typename T, int TD, bool BOX, bool DX, bool DY, bool RES = false, int STG = 0>
 __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const DevGrid& dst, T g, const T (&c9)[9],
-                                                   int x0, int y0, int yend, double* residual = nullptr) {
+                                                   int x0, int y0, int yend, double* residual = nullptr,
+                                                   const T* c9b = nullptr, T alpha = (T)0) {
+    static_assert(STG == 0 || TD == 2, "a two-stage step is two levels");
     typedef typename WMask<T>::type M;
     constexpr int G = TD;
     const int lane = threadIdx.x & 63;
@@ -157,23 +161,29 @@ __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const Dev
         for (int k = 1; k <= TD; ++k) {
             const int yk = j - k;
             const T(*r)[3] = ring[k - 1];
+            // STG: level 2 applies the second stencil, plus alpha times the
+            // starting state at row yk (level 0's oldest row, still held)
+            // (k is a compile-time index: each level reads one table directly)
+            auto c = [&](int t) -> T { return (STG && k == 2) ? c9b[t] : c9[t]; };
+            const bool with_alpha = STG == 2 && k == 2;
+            const T a0 = with_alpha ? alpha * ring[0][S0][1] : (T)0;
             T v;
             if (BOX) {
-                v = c9[0] * r[S0][0];
-                v = fma(c9[1], r[S0][1], v);
-                v = fma(c9[2], r[S0][2], v);
-                v = fma(c9[3], r[S1][0], v);
-                v = fma(c9[4], r[S1][1], v);
-                v = fma(c9[5], r[S1][2], v);
-                v = fma(c9[6], r[S2][0], v);
-                v = fma(c9[7], r[S2][1], v);
-                v = fma(c9[8], r[S2][2], v);
+                v = with_alpha ? fma(c(0), r[S0][0], a0) : c(0) * r[S0][0];
+                v = fma(c(1), r[S0][1], v);
+                v = fma(c(2), r[S0][2], v);
+                v = fma(c(3), r[S1][0], v);
+                v = fma(c(4), r[S1][1], v);
+                v = fma(c(5), r[S1][2], v);
+                v = fma(c(6), r[S2][0], v);
+                v = fma(c(7), r[S2][1], v);
+                v = fma(c(8), r[S2][2], v);
             } else {
-                v = c9[1] * r[S0][1];
-                v = fma(c9[3], r[S1][0], v);
-                v = fma(c9[4], r[S1][1], v);
-                v = fma(c9[5], r[S1][2], v);
-                v = fma(c9[7], r[S2][1], v);
+                v = with_alpha ? fma(c(1), r[S0][1], a0) : c(1) * r[S0][1];
+                v = fma(c(3), r[S1][0], v);
+                v = fma(c(4), r[S1][1], v);
+                v = fma(c(5), r[S1][2], v);
+                v = fma(c(7), r[S2][1], v);
             }
             if (DX) v = wblend(live, v, g);
             if (DY && (yk < 0 || yk >= ny)) v = g;

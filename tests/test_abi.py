@@ -337,6 +337,38 @@ def test_asymmetric_halo_validation():
     assert apply(tight, agrid((1, 0, 0), (0, 0, 0), origin=far()), s, bc()) == E
 
 
+def test_stages_validation():
+    E, H, U, NODEV = (_lib.LOPE_ERR_INVALID_ARG, _lib.LOPE_ERR_HALO_TOO_SMALL, _lib.LOPE_ERR_UNSUPPORTED,
+                      _lib.LOPE_ERR_NO_DEVICE)
+    s1, _k1 = stencil(r=1)
+    star3 = np.zeros((7, 7, 7))                    # radius-3 star: 19 non-zero taps
+    star3[3, 3, :] = star3[3, :, 3] = star3[:, 3, 3] = 0.05
+    s3 = _lib.lope_stencil()
+    s3.ndim, s3.radius = 3, 3
+    s3.coeffs = star3.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    big, _kb = stencil(r=2)                        # 125 non-zero taps
+    idx = ctypes.c_int32(5)
+
+    def run(a, b, first, second, n=2, out=True):
+        sg = _lib.lope_stages(ctypes.pointer(first) if first is not None else None,
+                              ctypes.pointer(second) if second is not None else None, 0.5)
+        return L.lope_iterate_stages(ctypes.byref(a), ctypes.byref(b), ctypes.byref(sg), ctypes.byref(bc()), n,
+                                     None, ctypes.byref(idx) if out else None)
+
+    assert run(grid(), grid(origin=far()), s1, s3) == NODEV      # only the first stencil's reach counts
+    assert run(grid(), grid(origin=far()), s3, s1) == H
+    assert run(grid(), grid(origin=far()), s1, None) == E
+    assert run(grid(), grid(origin=far()), s1, s1, n=-1) == E
+    assert run(grid(), grid(origin=far()), s1, s1, out=False) == E
+    assert run(grid(h=2), grid(h=2, origin=far()), big, s1) == U
+    assert run(grid(), grid(), s1, s1) == _lib.LOPE_ERR_ALIAS
+    sg = _lib.lope_stages(ctypes.pointer(s1), ctypes.pointer(s1), 0.5)
+    assert L.lope_apply_stages(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), None, ctypes.byref(bc()),
+                               None) == E
+    assert L.lope_apply_stages(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), ctypes.byref(sg),
+                               ctypes.byref(bc()), None) == NODEV
+
+
 def test_committed_tuning_table_registers_completely():
     import json
     from paper_1502_03504_amd import tune
