@@ -7,9 +7,13 @@
 // (R rows above and below, R columns left and right; the star needs no
 // corners) is published in LDS, double-buffered, one barrier per plane.
 // Core planes are fetched R+1+PF planes ahead of the plane being computed
-// and halos PF planes ahead (PF = 1 or 2 alternating prefetch buffers), so
-// the loads of the next PF steps are in flight while this one computes; the
-// deeper prefetch costs registers, which the wider stencils cannot spare.
+// and halos HPF planes ahead (PF, HPF = 1 or 2 alternating prefetch
+// buffers), so the loads of the next steps are in flight while this one
+// computes; the deeper prefetch costs registers, which the wider stencils
+// can spare for the halo (one vector per thread) but not for the core.  The
+// x halo is loaded as whole aligned vectors once at least half of each
+// vector is used.  WPE (waves per SIMD asked of the register allocator;
+// 1 = no request) holds the allocation to the occupancy the tile needs.
 //
 // The LDS row holds the core at a 16-byte aligned column (kLead) so the
 // centre and y-neighbour rows are read as vectors.  Every point is summed as
@@ -43,8 +47,8 @@ struct Vec<double> {
     static constexpr int n = 2;
 };
 
-template <typename T, int R, int BX, int BY, int NT, int PF>
-__global__ void __launch_bounds__(NT)
+template <typename T, int R, int BX, int BY, int NT, int PF, int HPF, int WPE>
+__global__ void __launch_bounds__(NT, WPE)
 k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chunk, int tiles_x, int tiles_y,
              int nblocks, int nblocks_padded) {
     typedef typename Vec<T>::type VT;
@@ -57,10 +61,16 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
     constexpr int LH = BY + 2 * R;          // LDS rows (core at row R)
     constexpr int RING = 2 * R + 1;
     constexpr int NHROW = 2 * R * TX;       // halo row vectors (R rows above, R below)
-    constexpr int NHCOL = 2 * R * BY;       // halo column scalars (R left, R right)
+    // x halo: whole aligned vectors (the kLead columns left and right of each
+    // core row) once a vector holds at least half useful values, else the R
+    // columns as scalars
+    constexpr bool kVecCols = 2 * R >= VEC;
+    constexpr int NCV = kLead / VEC;        // x-halo vectors per side per row
+    constexpr int NHCOL = kVecCols ? 2 * NCV * BY : 2 * R * BY;
     constexpr int NHALO = NHROW + NHCOL;
     constexpr int HPT = (NHALO + NT - 1) / NT;   // halo items per thread
     static_assert(BX % VEC == 0 && NT % TX == 0 && BY % TYT == 0, "tile shape");
+    static_assert((PF == 1 || PF == 2) && (HPF == 1 || HPF == 2), "the march is unrolled by two");
 
     __shared__ __attribute__((aligned(16))) T lds[2][LH][LW];
 
@@ -150,6 +160,20 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) hv[m][e] = elem(gx + e, gy, zo);
                 }
+            } else if constexpr (kVecCols) {
+                const int c = h - NHROW;
+                const int side = c / (NCV * BY), rem = c % (NCV * BY);
+                const int cv = rem / BY, gy = y0 + rem % BY;
+                const int gx = side == 0 ? x0 - kLead + cv * VEC : x0 + BX + cv * VEC;
+                if (gx >= 0 && gx + VEC <= nx && (gy < ny || pery)) {
+                    const int64_t o = zo + (int64_t)wrap_index(gy, ny) * src.sy + gx;
+                    const VT q = *(const VT*)(sp + o);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) hv[m][e] = ((const T*)&q)[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) hv[m][e] = elem(gx + e, gy, zo);
+                }
             } else {
                 const int c = h - NHROW;
                 const int side = c / (R * BY), rem = c % (R * BY);
@@ -169,6 +193,13 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
                 const int ly = r < R ? r : BY + r;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) L[ly][kLead + hx * VEC + e] = hv[m][e];
+            } else if constexpr (kVecCols) {
+                const int c = h - NHROW;
+                const int side = c / (NCV * BY), rem = c % (NCV * BY);
+                const int cv = rem / BY, row = rem % BY;
+                const int lx = side == 0 ? cv * VEC : kLead + BX + cv * VEC;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) L[R + row][lx + e] = hv[m][e];
             } else {
                 const int c = h - NHROW;
                 const int side = c / (R * BY), rem = c % (R * BY);
@@ -180,10 +211,10 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
     };
 
     T ring[RPT][RING][VEC];
-    T preA[RPT][VEC], preB[RPT][VEC];
-    T hA[HPT][VEC], hB[HPT][VEC];
+    T pre[PF][RPT][VEC];
+    T hal[HPF][HPT][VEC];
     // prologue: planes z0-R .. z0+R into the ring, centre plane z0 into LDS[0],
-    // then the next two core planes and halos in flight
+    // then the next PF core planes and HPF halos in flight
 #pragma unroll
     for (int s = 0; s < RING; ++s) {
         T tmp[RPT][VEC];
@@ -193,25 +224,28 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
 #pragma unroll
             for (int e = 0; e < VEC; ++e) ring[k][s][e] = tmp[k][e];
     }
-    load_halo(z0, hA);
-    store_halo(lds[0], hA);
+    load_halo(z0, hal[0]);
+    store_halo(lds[0], hal[0]);
 #pragma unroll
     for (int k = 0; k < RPT; ++k)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) lds[0][R + ty + k * TYT][kLead + tx * VEC + e] = ring[k][R][e];
-    load_core(z0 + R + 1, preA);
-    load_halo(z0 + 1, hA);
-    if constexpr (PF == 2) {
-        load_core(z0 + R + 2, preB);
-        load_halo(z0 + 2, hB);
-    }
+#pragma unroll
+    for (int p = 0; p < PF; ++p) load_core(z0 + R + 1 + p, pre[p]);
+#pragma unroll
+    for (int q = 0; q < HPF; ++q) load_halo(z0 + 1 + q, hal[q]);
     lds_barrier();
 
     // One march step: compute plane zc, shift in core plane zc+R+1 (held in
-    // pre), publish plane zc+1 (halo in hp), then refill pre/hp with the
-    // planes two steps ahead.  Steps alternate between two prefetch buffers.
-    auto step = [&](int zc, T (&pre)[RPT][VEC], T (&hp)[HPT][VEC]) {
-        const int buf = (zc - z0) & 1;
+    // pre[U % PF]), publish plane zc+1 (its halo in hal[U % HPF]), then
+    // refill those buffers with the planes PF and HPF steps ahead.  U is the
+    // step's position in the two-step unrolled loop, so buffer indices are
+    // compile-time constants.
+    auto step = [&](int zc, auto U) {
+        constexpr int u = decltype(U)::value;
+        T (&cur)[RPT][VEC] = pre[u % PF];
+        T (&hp)[HPT][VEC] = hal[u % HPF];
+        constexpr int buf = u;
         T (*L)[LW] = lds[buf];
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
@@ -253,7 +287,7 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
             for (int e = 0; e < VEC; ++e) {
 #pragma unroll
                 for (int s = 0; s < RING - 1; ++s) ring[k][s][e] = ring[k][s + 1][e];
-                ring[k][RING - 1][e] = pre[k][e];
+                ring[k][RING - 1][e] = cur[k][e];
             }
         if (zc + 1 < zend) {
             T (*N)[LW] = lds[buf ^ 1];
@@ -262,22 +296,18 @@ k_star3d_vec(DevGrid src, DevGrid dst, DevRule rule, VStarCoef<T, R> cf, int chu
             for (int k = 0; k < RPT; ++k)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) N[R + ty + k * TYT][kLead + tx * VEC + e] = ring[k][R][e];
-            if (zc + PF < zend) {
-                load_core(zc + R + 1 + PF, pre);
-                load_halo(zc + 1 + PF, hp);
-            }
+            if (zc + PF < zend) load_core(zc + R + 1 + PF, cur);
+            if (zc + 1 + HPF < zend) load_halo(zc + 1 + HPF, hp);
         }
         lds_barrier();
     };
-    for (int zc = z0; zc < zend; zc += PF) {
-        step(zc, preA, hA);
-        if constexpr (PF == 2) {
-            if (zc + 1 < zend) step(zc + 1, preB, hB);
-        }
+    for (int zc = z0; zc < zend; zc += 2) {
+        step(zc, std::integral_constant<int, 0>{});
+        if (zc + 1 < zend) step(zc + 1, std::integral_constant<int, 1>{});
     }
 }
 
-template <typename T, int R, int BX, int BY, int NT, int PF>
+template <typename T, int R, int BX, int BY, int NT, int PF, int HPF, int WPE>
 hipError_t run_star3d_vec(const SweepJob& j, int chunk, hipStream_t s) {
     VStarCoef<T, R> cf;
     const int r = j.radius;
@@ -296,16 +326,18 @@ hipError_t run_star3d_vec(const SweepJob& j, int chunk, hipStream_t s) {
     if (nb64 > (1ll << 30)) return hipErrorInvalidConfiguration;
     const int nb = (int)nb64;
     const int nbp = padded_block_count(nb);
-    hipLaunchKernelGGL((k_star3d_vec<T, R, BX, BY, NT, PF>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, j.rule, cf, chunk,
+    hipLaunchKernelGGL((k_star3d_vec<T, R, BX, BY, NT, PF, HPF, WPE>), dim3(nbp), dim3(NT), 0, s, j.src, j.dst, j.rule, cf, chunk,
                        tiles_x, tiles_y, nb, nbp);
     return hipGetLastError();
 }
 
-#define VSTAR(T, DT, R, BX, BY, NT, PF, CH)                                                                \
-    {"star3dv_" #T "_r" #R "_t1_" #BX "x" #BY "_nt" #NT "_pf" #PF, FAM_STAR3D_VEC, 3, R, 1, DT, 0, BX, BY, NT, \
-     CH, &run_star3d_vec<T, R, BX, BY, NT, PF>}
+#define VSTARH(T, DT, R, BX, BY, NT, PF, HPF, NAME, CH, WPE)                                              \
+    {"star3dv_" #T "_r" #R "_t1_" #BX "x" #BY "_nt" #NT "_pf" NAME, FAM_STAR3D_VEC, 3, R, 1, DT, 0, BX, BY, NT, \
+     CH, &run_star3d_vec<T, R, BX, BY, NT, PF, HPF, WPE>}
+#define VSTAR(T, DT, R, BX, BY, NT, PF, CH) VSTARH(T, DT, R, BX, BY, NT, PF, PF, #PF, CH, 1)
 
-// PF: planes fetched ahead (1 or 2 prefetch buffers)
+// PF: core planes fetched ahead (1 or 2 prefetch buffers); halos as many
+// planes ahead unless the name says otherwise ("pf1h2": core 1, halo 2)
 const Variant kStar3dVec[] = {
     VSTAR(float, LOPE_F32, 1, 128, 16, 256, 2, 32),
     VSTAR(float, LOPE_F32, 1, 128, 32, 512, 2, 32),
@@ -319,6 +351,9 @@ const Variant kStar3dVec[] = {
     VSTAR(float, LOPE_F32, 4, 64, 16, 256, 1, 128),
     VSTAR(float, LOPE_F32, 4, 64, 16, 256, 2, 128),
     VSTAR(float, LOPE_F32, 4, 128, 16, 512, 1, 128),
+    VSTARH(float, LOPE_F32, 4, 64, 16, 256, 1, 2, "1h2", 128, 4),
+    VSTARH(float, LOPE_F32, 4, 64, 32, 512, 1, 2, "1h2", 128, 4),
+    VSTARH(float, LOPE_F32, 4, 128, 16, 512, 1, 2, "1h2", 128, 4),
     VSTAR(double, LOPE_F64, 1, 64, 16, 256, 2, 32),
     VSTAR(double, LOPE_F64, 1, 64, 16, 256, 1, 32),
     VSTAR(double, LOPE_F64, 1, 32, 32, 256, 1, 32),
