@@ -364,7 +364,9 @@ int lope_select_variant(const lope_grid* g, const lope_stencil* st, int32_t tdep
  * 0 = lope_iterate with tdepth 0 (automatic), k = lope_iterate with tdepth k
  * (then the variant's own depth must be k).  The key is (ndim, radius,
  * dtype, star/box shape, size bucket = floor(log2(interior points)),
- * requested depth).  Only structural checks are made (no device access). */
+ * requested depth).  tune->variant = 0 removes the choice registered for that
+ * request (tdepth 0..4), so the request falls back to the default variant.
+ * Only structural checks are made (no device access). */
 int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning* tune);
 
 #ifdef __cplusplus

@@ -314,6 +314,8 @@ struct Registry {
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = plane2d_wave_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
+        n = star3d_wave_variants(&p);
+        for (int i = 0; i < n; ++i) v.push_back(p[i]);
     }
 };
 Registry& registry() {
@@ -338,7 +340,7 @@ TuneKey tune_key(int ndim, int radius, int dtype, bool star, int64_t points, int
 bool variant_fits(const Variant& v, const SweepJob& j, int tdepth) {
     if (v.ndim != j.ndim || v.radius != j.radius || v.dtype != j.dtype || v.tdepth != tdepth) return false;
     if (v.family == FAM_STAR3D) return j.star;
-    if (v.family == FAM_STAR3D_FLAT) {   // in-plane byte offsets within 31 bits
+    if (v.family == FAM_STAR3D_FLAT || v.family == FAM_STAR3D_WAVE) {   // in-plane byte offsets within 31 bits
         const int64_t esize = j.dtype == LOPE_F64 ? 8 : 4;
         return j.star && j.src.sz * esize < ((int64_t)1 << 31) && j.dst.sz * esize < ((int64_t)1 << 31);
     }
@@ -477,19 +479,16 @@ int iterate_impl(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
     int64_t done = 0, passes = 0;
     while (done < n_steps) {
         int64_t left = n_steps - done;
-        int depth = plan.tdepth;
-        int variant = plan.variant;
-        if (left < depth && variant > 0) {  // remainder: the best variant of that smaller depth
-            depth = (int)left;
-            variant = default_variant(job, depth);
-            if (!variant) {
-                depth = 1;
-                variant = default_variant(job, 1);
-            }
+        int variant = plan.variant, chunk = plan.chunk;
+        if (left < plan.tdepth && variant > 0) {
+            // remainder: the tuned (else the first fitting) variant of at most `left` sweeps
+            const Plan rp = choose(job, (int)left, 0, 0);
+            variant = rp.variant;
+            chunk = rp.chunk;
         }
         job.src = (passes & 1) ? gb : ga;
         job.dst = (passes & 1) ? ga : gb;
-        if ((rc = run_pass(job, variant, variant == plan.variant ? plan.chunk : 0, s))) return rc;
+        if ((rc = run_pass(job, variant, chunk, s))) return rc;
         done += variant > 0 ? registry().v[variant - 1].tdepth : 1;
         ++passes;
     }
@@ -1174,8 +1173,15 @@ int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning*
     lope_bc bc{};
     for (int a = 0; a < 3; ++a) bc.kind[a] = LOPE_BC_PERIODIC;
     build_job(job, g, g, st, &bc, false);
-    int td = tune->variant > 0 ? registry().v[tune->variant - 1].tdepth : 1;
-    if (tune->variant > 0 && !variant_fits(registry().v[tune->variant - 1], job, td))
+    if (tune->variant == 0) {   // remove the choice for this request
+        if (tune->tdepth < 0 || tune->tdepth > 4) return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 0..4", tune->tdepth);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.erase(tune_key(job.ndim, job.radius, job.dtype, job.star, (int64_t)job.src.nx * job.src.ny * job.src.nz,
+                              tune->tdepth));
+        return LOPE_OK;
+    }
+    const int td = registry().v[tune->variant - 1].tdepth;
+    if (!variant_fits(registry().v[tune->variant - 1], job, td))
         return fail(LOPE_ERR_UNSUPPORTED, "variant %d does not fit this grid/stencil", tune->variant);
     if (tune->tdepth < 0 || tune->tdepth > 4 || (tune->tdepth > 0 && tune->tdepth != td))
         return fail(LOPE_ERR_INVALID_ARG, "tdepth %d: 0 (automatic) or the variant's own depth %d", tune->tdepth, td);

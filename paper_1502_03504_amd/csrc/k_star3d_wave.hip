@@ -1,0 +1,350 @@
+// 3D radius-1 star (7 taps), TD sweeps fused per pass, one wavefront per
+// brick: 64 x columns (one per lane) by P + 2*TD rows, marching a z-chunk.
+// No LDS and no barriers.
+//
+// The 64 lanes hold 64 consecutive columns; the wave's outputs are the middle
+// 64 - 2*TD columns and the middle P rows (each fused sweep consumes one
+// column and one row of halo on each side, as in the 2D wave kernel).  Each
+// lane keeps a column of NR = P + 2*TD rows in registers: the y neighbours of
+// a row are the rows above and below in the same lane, the x neighbours come
+// from lanes l-1 and l+1 as DPP operands of the fmas themselves (no separate
+// moves; float32), and the z direction is the march.
+//
+// Instead of a ring of three input planes per level, each level keeps two
+// partial sums: when level k's plane q is complete it finishes level k+1's
+// plane q-1 (its z+1 tap), adds the in-plane taps to plane q (y-1, x-1,
+// centre, x+1, y+1) and starts plane q+1 with its z-1 tap.  The taps of every
+// point are therefore summed as c(z-1)*v followed by fmas in lexicographic
+// offset order, the same chain as every other kernel.  Level k completes
+// plane j - k at march step j (level 0 is the plane loaded at step j); the
+// march runs from z0 - TD to zend - 1 + TD and stores level TD's planes
+// [z0, zend).  Values outside the cone of the stored outputs are computed
+// and thrown away (garbage lanes at the wave's edges move one lane inward per
+// level and never reach an output lane).
+//
+// Boundary rule: a periodic axis loads the wrapped column / row / plane; a
+// lane outside a Dirichlet x axis holds g at every level (bit blend, DXY), a
+// row outside a Dirichlet y axis is g at every level (DXY; a wave-uniform
+// choice per row) and a plane outside a Dirichlet z axis is g at every level
+// (DZ).
+//
+// Planes are prefetched PF steps ahead (PF = 1 or 3; the march is unrolled by
+// three, the period of the partial-sum ring, so every buffer index is a
+// compile-time constant and no value moves between registers).  Loads and
+// stores go through a buffer resource per plane: the plane's base in scalar
+// registers, a 32-bit in-plane offset per lane and row (loop-invariant), and
+// the hardware's range check (the caller checks plane sizes below 2^31
+// bytes; every offset is inside the plane anyway).
+#include "plane2d_wave.h"
+
+namespace lope {
+namespace {
+
+template <typename T>
+struct Coef7 {
+    T c[7];   // z-1, y-1, x-1, centre, x+1, y+1, z+1
+};
+
+// Buffer resource of one plane: base address, size in bytes (accesses past
+// it read 0 and write nothing), the gfx9 data-format word.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+// (the builtins move raw bits: the values are reinterpreted, not converted)
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+constexpr int kBufferNontemporal = 2;   // cache-policy bits of a streaming store
+__device__ __forceinline__ void buffer_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, kBufferNontemporal);
+}
+__device__ __forceinline__ void buffer_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, kBufferNontemporal);
+}
+
+// a[i] + c(x-1) * v[i][lane-1] + c(x) * v[i] + c(x+1) * v[i][lane+1] for N
+// rows (N <= 3), three fmas per row in that order, with the lane shifts folded
+// into the fmas (DPP operands: lanes past the wave's ends read 0).  cm, cp in
+// VGPRs (a DPP fma takes its second factor from a VGPR), c0 in an SGPR.  A DPP
+// instruction must not read a VGPR the VALU wrote in the two wait states
+// before: one s_nop covers the inputs, and with three rows interleaved every
+// accumulator is two instructions old when its second DPP fma reads it (one
+// or two rows add an s_nop).
+__device__ __forceinline__ void fma_xrows(float& a0, float& a1, float& a2, float v0, float v1, float v2, float cm, float c0,
+                                          float cp) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %3, %6 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %4, %6 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %2, %5, %6 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_e32 %0, %8, %3\n\t"
+        "v_fmac_f32_e32 %1, %8, %4\n\t"
+        "v_fmac_f32_e32 %2, %8, %5\n\t"
+        "v_fmac_f32_dpp %0, %3, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %4, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %2, %5, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(a0), "+v"(a1), "+v"(a2)
+        : "v"(v0), "v"(v1), "v"(v2), "v"(cm), "v"(cp), "s"(c0));
+}
+__device__ __forceinline__ void fma_xrows(float& a0, float& a1, float v0, float v1, float cm, float c0, float cp) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %2, %4 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %3, %4 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_e32 %0, %6, %2\n\t"
+        "v_fmac_f32_e32 %1, %6, %3\n\t"
+        "s_nop 0\n\t"
+        "v_fmac_f32_dpp %0, %2, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %3, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(a0), "+v"(a1)
+        : "v"(v0), "v"(v1), "v"(cm), "v"(cp), "s"(c0));
+}
+__device__ __forceinline__ void fma_xrows(float& a0, float v0, float cm, float c0, float cp) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_e32 %0, %4, %1\n\t"
+        "s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(a0)
+        : "v"(v0), "v"(cm), "v"(cp), "s"(c0));
+}
+// float64: the shifts as DPP moves (a 64-bit value is two 32-bit moves)
+__device__ __forceinline__ void fma_xrows(double& a0, double v0, double cm, double c0, double cp) {
+    a0 = fma(cm, wave_shift<kDppWaveShr1>(v0), a0);
+    a0 = fma(c0, v0, a0);
+    a0 = fma(cp, wave_shift<kDppWaveShl1>(v0), a0);
+}
+__device__ __forceinline__ void fma_xrows(double& a0, double& a1, double v0, double v1, double cm, double c0,
+                                          double cp) {
+    fma_xrows(a0, v0, cm, c0, cp);
+    fma_xrows(a1, v1, cm, c0, cp);
+}
+__device__ __forceinline__ void fma_xrows(double& a0, double& a1, double& a2, double v0, double v1, double v2,
+                                          double cm, double c0, double cp) {
+    fma_xrows(a0, v0, cm, c0, cp);
+    fma_xrows(a1, v1, cm, c0, cp);
+    fma_xrows(a2, v2, cm, c0, cp);
+}
+
+// RES: also merge max |u_TD - u_(TD-1)| over the stored outputs (the change
+// made by the last sweep) into the device double `residual`.
+template <typename T, int TD, int P, int NW, bool DXY, bool DZ, bool RES, int PF, int WPE>
+__global__ void __launch_bounds__(NW * 64, WPE)
+k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, int chunk, int strips, int segs, int nwaves,
+              int nblocks_padded, double* residual) {
+    static_assert(PF == 1 || PF == 3, "the march is unrolled by three");
+    typedef typename WMask<T>::type M;
+    constexpr int G = TD;
+    constexpr int NR = P + 2 * G;
+    // the wave index is uniform: rows, planes and loop bounds stay scalar
+    const int wave = xcd_logical_block(nblocks_padded) * NW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wave >= nwaves) return;   // whole waves leave; there is no barrier
+    const int tx = wave % strips, rest = wave / strips;
+    const int ty = rest % segs, tz = rest / segs;
+    const int nx = src.nx, ny = src.ny, nz = src.nz;
+    const int x0 = tx * (64 - 2 * G), y0 = ty * P, z0 = tz * chunk;
+    const int zend = min(z0 + chunk, nz), yend = min(y0 + P, ny);
+    const bool perx = rule.per[0] != 0, pery = rule.per[1] != 0;
+    const T g = (T)rule.g;
+
+    const int lane = threadIdx.x & 63;
+    const int gx = x0 - G + lane;
+    const bool ox = gx < 0 || gx >= nx;
+    const int wx = perx ? wrap_index(gx, nx) : min(max(gx, 0), nx - 1);
+    const M live = (DXY && !perx && ox) ? (M)0 : ~(M)0;
+    const bool keep = lane >= G && lane < 64 - G && gx < nx;
+
+    // rows: in-plane byte offsets of this lane's (wrapped or clamped) column
+    // in each row, and which rows lie outside a Dirichlet y axis (g at every
+    // level)
+    unsigned boff[NR];
+    unsigned grow = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int y = y0 - G + r;
+        if (DXY && !pery && (y < 0 || y >= ny)) grow |= 1u << r;
+        const int yw = pery ? wrap_index(y, ny) : min(max(y, 0), ny - 1);
+        boff[r] = ((unsigned)yw * (unsigned)src.sy + (unsigned)wx) * (unsigned)sizeof(T);
+    }
+    auto is_grow = [&](int r) { return DXY && ((grow >> r) & 1u); };
+
+    const char* sp = (const char*)src.origin;
+    const char* dp = (const char*)dst.origin;
+    const int64_t szb = src.sz * (int64_t)sizeof(T), dszb = dst.sz * (int64_t)sizeof(T);
+    // Plane q of level 0 (every row loaded: the index is wrapped, or clamped
+    // and then replaced by g outside a Dirichlet z axis).
+    auto load_plane = [&](int q, T (&v)[NR]) {
+        const int qw = DZ ? min(max(q, 0), nz - 1) : wrap_index(q, nz);
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(sp + qw * szb, szb);
+        const bool gz = DZ && (q < 0 || q >= nz);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const T t = buffer_load<T>(rs, boff[r]);
+            v[r] = (is_grow(r) || gz) ? g : t;
+        }
+    };
+
+    // acc[k][s][r]: partial sums of level k+1, a ring of three planes (two in
+    // flight; the third slot is free between finishing one and starting one)
+    T acc[TD][3][NR];
+#pragma unroll
+    for (int k = 0; k < TD; ++k)
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[k][s][r] = (T)0;
+
+    const int jstart = z0 - TD, jend = zend - 1 + TD;
+    T pf[PF][NR];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) load_plane(jstart + q, pf[q]);
+
+    const unsigned xoff = (unsigned)(keep ? gx : 0) * (unsigned)sizeof(T);
+    double rmax = 0.0;   // RES: this lane's maximum change over its outputs
+    T prev[NR];          // RES: level TD-1's previous plane (rows TD .. NR-TD-1)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) prev[r] = (T)0;
+    const unsigned dsyb = (unsigned)dst.sy * (unsigned)sizeof(T);
+    // March step j (phase u of the three-step unroll): level 0 is the plane in
+    // pf[u % PF]; once consumed, that buffer takes the plane PF steps ahead
+    // (past the end: a repeat of the last plane, never used).
+    auto step = [&](int j, auto phase) {
+        constexpr int u = decltype(phase)::value;
+        T cur[NR];
+#pragma unroll
+        for (int k = 0; k < TD; ++k) {
+            // level k's plane q = j - k, rows [k, NR - k) valid
+            T(&lv)[NR] = k == 0 ? pf[u % PF] : cur;
+            T(&old)[NR] = acc[k][u];             // level k+1, plane q - 1
+            T(&mid)[NR] = acc[k][(u + 1) % 3];   // level k+1, plane q
+            T(&nw)[NR] = acc[k][(u + 2) % 3];    // level k+1, plane q + 1
+            T nxt[NR], bl[NR];
+#pragma unroll
+            for (int r = k; r < NR - k; ++r) bl[r] = k == 0 && DXY ? wblend(live, lv[r], g) : lv[r];
+            // rows lo .. hi-1 of level k+1: y-1 tap, x taps (three rows at a
+            // time), y+1 tap; then the z+1 tap finishes plane q-1 and the z-1
+            // tap starts plane q+1
+            const int lo = k + 1, hi = NR - 1 - k;
+#pragma unroll
+            for (int r = lo; r < hi; ++r) mid[r] = fma(cf.c[1], bl[r - 1], mid[r]);
+#pragma unroll
+            for (int r = lo; r < hi; r += 3) {
+                if (r + 3 <= hi)
+                    fma_xrows(mid[r], mid[r + 1], mid[r + 2], bl[r], bl[r + 1], bl[r + 2], cf.c[2], cf.c[3], cf.c[4]);
+                else if (r + 2 == hi)
+                    fma_xrows(mid[r], mid[r + 1], bl[r], bl[r + 1], cf.c[2], cf.c[3], cf.c[4]);
+                else
+                    fma_xrows(mid[r], bl[r], cf.c[2], cf.c[3], cf.c[4]);
+            }
+#pragma unroll
+            for (int r = lo; r < hi; ++r) {
+                mid[r] = fma(cf.c[5], bl[r + 1], mid[r]);
+                nxt[r] = fma(cf.c[6], bl[r], old[r]);
+                nw[r] = cf.c[0] * bl[r];
+            }
+            if (k == 0) load_plane(min(j + PF, jend), pf[u % PF]);
+            // the rule on the completed plane p of level k+1
+            const int p = j - k - 1;
+            const bool gz = DZ && (p < 0 || p >= nz);
+#pragma unroll
+            for (int r = k + 1; r < NR - 1 - k; ++r) {
+                T v = DXY ? wblend(live, nxt[r], g) : nxt[r];
+                if (is_grow(r) || gz) v = g;
+                nxt[r] = v;
+            }
+            if (k + 1 < TD) {
+#pragma unroll
+                for (int r = k + 1; r < NR - 1 - k; ++r) cur[r] = nxt[r];
+            } else if (p >= z0 && p < zend && keep) {
+                const __amdgpu_buffer_rsrc_t rd = plane_rsrc(dp + p * dszb, dszb);
+#pragma unroll
+                for (int r = TD; r < NR - TD; ++r) {
+                    const int y = y0 + (r - TD);
+                    if (y < yend) {
+                        buffer_store(nxt[r], rd, (unsigned)y * dsyb + xoff);
+                        if (RES) rmax = nan_max(rmax, fabs((double)nxt[r] - (double)prev[r]));
+                    }
+                }
+            }
+            // RES: level TD-1's plane p + 1 is the state before the last sweep
+            // of the next step's outputs
+            if (RES && k + 1 == TD) {
+#pragma unroll
+                for (int r = TD; r < NR - TD; ++r) prev[r] = bl[r];
+            }
+        }
+    };
+    for (int j = jstart; j <= jend; j += 3) wave_steps<0, 3>(j, jend, step);
+    if (RES) residual_merge(rmax, residual);
+}
+
+template <typename T, int TD, int P, int NW, int PF, int WPE>
+hipError_t run_star3d_wave(const SweepJob& j, int chunk, hipStream_t s) {
+    Coef7<T> cf;
+    auto dense = [&](int ox, int oy, int oz) { return (T)j.dense[(ox + 1) + (oy + 1) * 3 + (oz + 1) * 9]; };
+    cf.c[0] = dense(0, 0, -1);
+    cf.c[1] = dense(0, -1, 0);
+    cf.c[2] = dense(-1, 0, 0);
+    cf.c[3] = dense(0, 0, 0);
+    cf.c[4] = dense(1, 0, 0);
+    cf.c[5] = dense(0, 1, 0);
+    cf.c[6] = dense(0, 0, 1);
+    if (chunk <= 0) chunk = 64;
+    const int out_cols = 64 - 2 * TD;
+    const int strips = (j.src.nx + out_cols - 1) / out_cols;
+    const int segs = (j.src.ny + P - 1) / P;
+    const int chunks = (j.src.nz + chunk - 1) / chunk;
+    const int64_t nw64 = (int64_t)strips * segs * chunks;
+    if (nw64 > (1ll << 30)) return hipErrorInvalidConfiguration;
+    const int nw = (int)nw64;
+    const int nbp = padded_block_count((nw + NW - 1) / NW);
+    const bool dxy = !j.rule.per[0] || !j.rule.per[1], dz = !j.rule.per[2];
+#define LOPE_WAVE3_LAUNCH(A, B, C)                                                                              \
+    hipLaunchKernelGGL((k_star3d_wave<T, TD, P, NW, A, B, C, PF, WPE>), dim3(nbp), dim3(NW * 64), 0, s, j.src,   \
+                       j.dst, j.rule, cf, chunk, strips, segs, nw, nbp, j.residual)
+#define LOPE_WAVE3_RULE(C)                 \
+    if (dxy && dz)                         \
+        LOPE_WAVE3_LAUNCH(true, true, C);  \
+    else if (dxy)                          \
+        LOPE_WAVE3_LAUNCH(true, false, C); \
+    else if (dz)                           \
+        LOPE_WAVE3_LAUNCH(false, true, C); \
+    else                                   \
+        LOPE_WAVE3_LAUNCH(false, false, C)
+    if (j.residual) {
+        LOPE_WAVE3_RULE(true);
+    } else {
+        LOPE_WAVE3_RULE(false);
+    }
+#undef LOPE_WAVE3_RULE
+#undef LOPE_WAVE3_LAUNCH
+    return hipGetLastError();
+}
+
+#define WSTAR(T, DT, TD, P, NW, PF, WPE, CH)                                                                \
+    {"star3dw_" #T "_r1_t" #TD "_p" #P "_pf" #PF "_nw" #NW "_w" #WPE, FAM_STAR3D_WAVE, 3, 1, TD, DT, 0,       \
+     64 - 2 * (TD), P, (NW) * 64, CH, &run_star3d_wave<T, TD, P, NW, PF, WPE>, 1, nullptr}
+
+// WPE: waves per SIMD asked of the register allocator (1 = no request)
+const Variant kStar3dWave[] = {
+    WSTAR(float, LOPE_F32, 4, 8, 4, 1, 1, 32),
+    WSTAR(float, LOPE_F32, 4, 10, 4, 1, 1, 32),
+    WSTAR(float, LOPE_F32, 4, 8, 2, 1, 1, 32),
+    WSTAR(float, LOPE_F32, 4, 6, 4, 1, 1, 32),
+    WSTAR(float, LOPE_F32, 4, 4, 4, 3, 1, 32),
+};
+
+}  // namespace
+
+int star3d_wave_variants(const Variant** out) {
+    *out = kStar3dWave;
+    return (int)(sizeof(kStar3dWave) / sizeof(kStar3dWave[0]));
+}
+
+}  // namespace lope

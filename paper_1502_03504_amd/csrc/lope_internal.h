@@ -64,7 +64,14 @@ hipError_t launch_residual_max(const DevGrid& x, const DevGrid& y, int dtype, do
 hipError_t launch_residual_zero(double* out, hipStream_t s);
 
 // Tuned kernel families.
-enum Family { FAM_GENERIC = 0, FAM_STAR3D = 1, FAM_PLANE2D = 2, FAM_STAR3D_VEC = 3, FAM_STAR3D_FLAT = 4 };
+enum Family {
+    FAM_GENERIC = 0,
+    FAM_STAR3D = 1,
+    FAM_PLANE2D = 2,
+    FAM_STAR3D_VEC = 3,
+    FAM_STAR3D_FLAT = 4,
+    FAM_STAR3D_WAVE = 5
+};
 
 typedef hipError_t (*VariantFn)(const SweepJob& j, int chunk, hipStream_t s);
 
@@ -94,6 +101,7 @@ struct Variant {
 // Registries filled by each kernel file.
 int star3d_variants(const Variant** out);
 int star3d_flat_variants(const Variant** out);
+int star3d_wave_variants(const Variant** out);
 int star3d_vec_variants(const Variant** out);
 int star3d_vtb_variants(const Variant** out);
 int plane2d_variants(const Variant** out);

@@ -239,9 +239,17 @@ def test_variant_selection_and_tuning_table():
     v2 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 2)
     L.lope_variant_info(v2, buf, 256)
     assert b"tdepth=2" in buf.value
+    v0 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0)
     t = _lib.lope_tuning(v2, 0, 32, 0)
     assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(t)) == 0
     assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0) == v2
+    # variant 0 removes the choice: the request falls back to the default
+    for req in (0, 3):
+        clear = _lib.lope_tuning(0, req, 0, 0)
+        assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(clear)) == 0
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0) == v0
+    bad = _lib.lope_tuning(0, 5, 0, 0)
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(bad)) == _lib.LOPE_ERR_INVALID_ARG
     box, _kb = stencil(ndim=3, r=1, fill=0.1)                            # 3D box: generic kernel
     assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(box), 1) == 0
 

@@ -102,6 +102,37 @@ def test_residual_is_exact_and_state_equals_plain_iteration(dtype):
         assert torch.equal((a, b)[idx].interior(), (c, d)[j].interior()), tdepth
 
 
+@pytest.mark.parametrize("kinds", [(P, P, P), (D, P, D), (P, D, P)])
+def test_residual_from_each_fused_3d_kernel(kinds):
+    """Every fused 3D radius-1 float32 kernel that reports the residual of its
+    last sweep, chosen through the tuning table, gives the exact residual and
+    the state of the plain iteration."""
+    from tests.gpu_util import variants_for
+    rng = np.random.default_rng([synth.CFG_TEST, 913])
+    st = synth.heat_star(3, 0.125)
+    u0 = rng.uniform(0, 1, (26, 19, 70)).astype(np.float32)
+    bc = (kinds, 0.3)
+    want_prev = _plain(u0, 1, st, bc, 11).interior()
+    want = _plain(u0, 1, st, bc, 12).interior()
+    fused = [(vid, info) for vid, info in variants_for(3, 1, np.float32)
+             if info.startswith(("star3dw_", "star3df_")) and "tdepth=1 " not in info]
+    assert any(info.startswith("star3dw_") for _, info in fused)
+    probe = grid_from(u0, 1)
+    try:
+        for vid, info in fused:
+            td = int(info.split("tdepth=")[1].split()[0])
+            L.lope_tune_set(probe, st, vid, td)
+            L.lope_tune_set(probe, st, vid, 0)
+            a, b = grid_from(u0, 1), empty_grid(u0.shape, 1, np.float32)
+            idx, steps, r = L.lope_iterate_until(a, b, st, bc, 12, 6, -1.0, tdepth=td)
+            assert steps == 12, info
+            assert torch.equal((a, b)[idx].interior(), want), info
+            assert r == _max_diff(want, want_prev), info
+    finally:
+        for td in (0, 2, 3, 4):
+            L.lope_tune_set(probe, st, 0, td)
+
+
 def test_special_cases():
     rng = np.random.default_rng([synth.CFG_TEST, 912])
     st = synth.heat_star(2, 0.125)

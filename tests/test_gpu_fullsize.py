@@ -59,6 +59,26 @@ def test_heat3d_512_f32_sampled_and_properties():
     assert float(out.min()) >= float(u.min()) - 1e-6 and float(out.max()) <= float(u.max()) + 1e-6
 
 
+def test_heat3d_512_f32_fused_kernels_bitwise():
+    """At the full size every fused 3D radius-1 float32 kernel (each wave-brick
+    variant and the automatic choice) gives the values of one sweep per pass,
+    bit for bit."""
+    from tests.gpu_util import variants_for
+    case = synth.case_heat3d(n=512, dtype=np.float32, steps=8)
+    u = case.field
+    ref = _run(u, case.stencil, case.bc, 8, tdepth=1).interior().clone()
+    assert torch.equal(_run(u, case.stencil, case.bc, 8, tdepth=0).interior(), ref)
+    waves = [(vid, info) for vid, info in variants_for(3, 1, np.float32) if info.startswith("star3dw_")]
+    assert waves
+    for vid, info in waves:
+        for chunk in (0, 100):
+            a = grid_from(u, 1)
+            b = a.empty_like()
+            idx = L.lope_iterate_tuned(a, b, case.stencil, case.bc, 8, variant=vid, chunk=chunk)
+            assert torch.equal((a, b)[idx].interior(), ref), (info, chunk)
+            del a, b
+
+
 def test_heat3d_512_f32_closed_form_mode():
     """A pure separable mode decays by lambda^n at the full size."""
     n, steps, rc = 512, 1000, 0.125
