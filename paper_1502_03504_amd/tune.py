@@ -197,3 +197,53 @@ def register_cache(path=None) -> int:
         if lib.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(t)) == 0:
             count += 1
     return count
+
+
+# The workloads the committed gfx950 table is tuned on: (name, case maker,
+# candidate z- or row-chunk lengths).  The cases are the seeded synthetic
+# inputs of the benchmark (package `synth` at the repository root).
+def _workloads():
+    import numpy as np
+    import synth
+    return [
+        ("heat3d512", lambda: synth.case_heat3d(512, np.float32, 10), (0, 16, 32, 64, 128)),
+        ("heat3d256f64", lambda: synth.case_heat3d(256, np.float64, 10), (0, 16, 32, 64, 128)),
+        ("box9", lambda: synth.case_box9(8192, 10), (0, 32, 64, 128, 256)),
+        ("star25", lambda: synth.case_star25(512, 10), (0, 32, 64, 128)),
+        ("heat2d", lambda: synth.case_heat2d(256, 10), (0, 2, 4, 8, 16, 32, 64)),
+    ]
+
+
+def tune_workloads(path, names=None, log=None):
+    """Time every fitting (variant, chunk) on the benchmark workloads and write
+    the choices to the JSON table at `path` (replaced).  Needs a GPU."""
+    from . import Grid
+    if os.path.exists(path):
+        os.remove(path)
+    out = {}
+    for name, make, chunks in _workloads():
+        if names and name not in names:
+            continue
+        case = make()
+        if log:
+            log("== %s" % name)
+        a = Grid.from_array(case.field, case.h)
+        b = a.empty_like()
+        best, _ = autotune(a, b, case.stencil, case.bc, sweeps=24, chunks=chunks, cache_path=path, log=log)
+        out[name] = best
+        if log:
+            log("best: %s" % best)
+        del a, b, case
+        torch.cuda.empty_cache()
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="re-tune the kernel table on the benchmark workloads")
+    ap.add_argument("--out", default=DEFAULT_CACHE, help="table to write (default: the committed one)")
+    ap.add_argument("names", nargs="*", help="workloads to tune (default: all)")
+    args = ap.parse_args()
+    tune_workloads(args.out, set(args.names) or None, log=lambda *m: print(*m, flush=True))
+    sys.exit(0)
