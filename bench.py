@@ -118,7 +118,7 @@ def measure_adjoint(n=256, steps=200, every=20):
             "ratio_end_to_end": round((t2 - t1) / (t1 - t0), 3)}
 
 
-def measure_batch(reps=3):
+def measure_batch(reps=3, per_grid=True):
     """512 uneven 2D float32 grids, 50 sweeps each: the batched launches against
     one launch per grid per sweep (median of reps, HIP events)."""
     import numpy as np
@@ -154,13 +154,14 @@ def measure_batch(reps=3):
     best = min(by_depth, key=by_depth.get)
     plan.set_depth(best)
     tb = by_depth[best]
-    tp = timed(plan.apply_per_grid)
+    tp = timed(plan.apply_per_grid) if per_grid else None
     plan.close()
     upd = points * steps
     return {"workload": "batch_512_grids_2d_f32_50_sweeps", "points": points, "tdepth": best,
-            "batched_ms": round(tb, 3), "per_grid_ms": round(tp, 3),
+            "batched_ms": round(tb, 3), "per_grid_ms": round(tp, 3) if tp else None,
             "batched_GPts": round(upd / (tb * 1e-3) / 1e9, 1),
-            "per_grid_GPts": round(upd / (tp * 1e-3) / 1e9, 1), "speedup": round(tp / tb, 2),
+            "per_grid_GPts": round(upd / (tp * 1e-3) / 1e9, 1) if tp else None,
+            "speedup": round(tp / tb, 2) if tp else None,
             "batched_ms_by_depth": {str(k): round(v, 3) for k, v in by_depth.items()},
             "launches_batched": -(-steps // best), "launches_per_grid": steps * len(grids)}
 
@@ -252,6 +253,9 @@ def main():
     ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size sweep workloads")
     ap.add_argument("--no-converge", action="store_true", help="skip the convergence-checked iteration")
     ap.add_argument("--no-stages", action="store_true", help="skip the two-stage (Heun) steps")
+    ap.add_argument("--reps", type=int, default=3, help="timed repeats of the batch and workload runs")
+    ap.add_argument("--no-per-grid", action="store_true",
+                    help="skip the one-launch-per-grid comparison of the batched workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -365,14 +369,14 @@ def main():
     batch = None
     if not args.no_batch:
         torch.cuda.empty_cache()
-        batch = measure_batch()
+        batch = measure_batch(reps=args.reps, per_grid=not args.no_per_grid)
         log("batch:", batch)
     copy_ref = measure_copy()
     log("copy:", copy_ref)
     workloads = None
     if not args.no_workloads:
         torch.cuda.empty_cache()
-        workloads = measure_workloads()
+        workloads = measure_workloads(reps=args.reps)
 
     cpu = None
     if args.cpu_sweeps > 0:
