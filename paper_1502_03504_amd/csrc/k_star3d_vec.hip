@@ -348,12 +348,11 @@ const Variant kStar3dVec[] = {
     VSTAR(float, LOPE_F32, 1, 256, 16, 512, 2, 32),
     VSTAR(float, LOPE_F32, 2, 64, 32, 256, 1, 64),
     VSTAR(float, LOPE_F32, 3, 64, 32, 256, 1, 64),
-    VSTAR(float, LOPE_F32, 4, 64, 16, 256, 1, 128),
-    VSTAR(float, LOPE_F32, 4, 64, 16, 256, 2, 128),
-    VSTAR(float, LOPE_F32, 4, 128, 16, 512, 1, 128),
-    VSTARH(float, LOPE_F32, 4, 64, 16, 256, 1, 2, "1h2", 128, 4),
+    VSTARH(float, LOPE_F32, 4, 64, 64, 1024, 1, 2, "1h2", 128, 4),
+    VSTARH(float, LOPE_F32, 4, 128, 32, 1024, 1, 2, "1h2", 128, 4),
     VSTARH(float, LOPE_F32, 4, 64, 32, 512, 1, 2, "1h2", 128, 4),
-    VSTARH(float, LOPE_F32, 4, 128, 16, 512, 1, 2, "1h2", 128, 4),
+    VSTARH(float, LOPE_F32, 4, 64, 16, 256, 1, 2, "1h2", 128, 4),
+    VSTAR(float, LOPE_F32, 4, 64, 16, 256, 1, 128),
     VSTAR(double, LOPE_F64, 1, 64, 16, 256, 2, 32),
     VSTAR(double, LOPE_F64, 1, 64, 16, 256, 1, 32),
     VSTAR(double, LOPE_F64, 1, 32, 32, 256, 1, 32),
