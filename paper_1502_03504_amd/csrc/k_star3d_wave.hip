@@ -57,17 +57,9 @@ template <>
 __device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
-template <>
-__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-}
 constexpr int kBufferNontemporal = 2;   // cache-policy bits of a streaming store
 __device__ __forceinline__ void buffer_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, kBufferNontemporal);
-}
-__device__ __forceinline__ void buffer_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, kBufferNontemporal);
 }
 
 // a[i] + c(x-1) * v[i][lane-1] + c(x) * v[i] + c(x+1) * v[i][lane+1] for N
@@ -114,24 +106,6 @@ __device__ __forceinline__ void fma_xrows(float& a0, float v0, float cm, float c
         : "+v"(a0)
         : "v"(v0), "v"(cm), "v"(cp), "s"(c0));
 }
-// float64: the shifts as DPP moves (a 64-bit value is two 32-bit moves)
-__device__ __forceinline__ void fma_xrows(double& a0, double v0, double cm, double c0, double cp) {
-    a0 = fma(cm, wave_shift<kDppWaveShr1>(v0), a0);
-    a0 = fma(c0, v0, a0);
-    a0 = fma(cp, wave_shift<kDppWaveShl1>(v0), a0);
-}
-__device__ __forceinline__ void fma_xrows(double& a0, double& a1, double v0, double v1, double cm, double c0,
-                                          double cp) {
-    fma_xrows(a0, v0, cm, c0, cp);
-    fma_xrows(a1, v1, cm, c0, cp);
-}
-__device__ __forceinline__ void fma_xrows(double& a0, double& a1, double& a2, double v0, double v1, double v2,
-                                          double cm, double c0, double cp) {
-    fma_xrows(a0, v0, cm, c0, cp);
-    fma_xrows(a1, v1, cm, c0, cp);
-    fma_xrows(a2, v2, cm, c0, cp);
-}
-
 // RES: also merge max |u_TD - u_(TD-1)| over the stored outputs (the change
 // made by the last sweep) into the device double `residual`.
 template <typename T, int TD, int P, int NW, bool DXY, bool DZ, bool RES, int PF, int WPE>
@@ -139,6 +113,9 @@ __global__ void __launch_bounds__(NW * 64, WPE)
 k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, int chunk, int strips, int segs, int nwaves,
               int nblocks_padded, double* residual) {
     static_assert(PF == 1 || PF == 3, "the march is unrolled by three");
+    // float64 would need two DPP moves per lane shift (no DPP form of the
+    // 64-bit fma) and twice the registers: the LDS designs serve it better
+    static_assert(std::is_same<T, float>::value, "float32 only");
     typedef typename WMask<T>::type M;
     constexpr int G = TD;
     constexpr int NR = P + 2 * G;
