@@ -106,6 +106,15 @@ __device__ __forceinline__ void fma_xrows(float& a0, float v0, float cm, float c
         : "+v"(a0)
         : "v"(v0), "v"(cm), "v"(cp), "s"(c0));
 }
+// f(integral_constant<S>) ... f(integral_constant<E-1>), unrolled at compile time
+template <int S, int E, typename F>
+__device__ __forceinline__ void static_steps(F&& f) {
+    if constexpr (S < E) {
+        f(std::integral_constant<int, S>{});
+        static_steps<S + 1, E>(f);
+    }
+}
+
 // RES: also merge max |u_TD - u_(TD-1)| over the stored outputs (the change
 // made by the last sweep) into the device double `residual`.
 template <typename T, int TD, int P, int NW, bool DXY, bool DZ, bool RES, int PF, int WPE>
@@ -188,14 +197,17 @@ k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, int chunk, in
 #pragma unroll
     for (int r = 0; r < NR; ++r) prev[r] = (T)0;
     const unsigned dsyb = (unsigned)dst.sy * (unsigned)sizeof(T);
-    // March step j (phase u of the three-step unroll): level 0 is the plane in
-    // pf[u % PF]; once consumed, that buffer takes the plane PF steps ahead
-    // (past the end: a repeat of the last plane, never used).
-    auto step = [&](int j, auto phase) {
+    // March step j (phase u = (j - jstart) mod 3 of the three-step unroll):
+    // level 0 is the plane in pf[u % PF]; once consumed, that buffer takes the
+    // plane PF steps ahead (past the end: a repeat of the last plane, never
+    // used).  Only levels k < KM run: during the first 2*TD steps level k+1
+    // has nothing valid to start before step 2k, so those steps skip it.
+    auto step = [&](int j, auto phase, auto kmax) __attribute__((always_inline)) {
         constexpr int u = decltype(phase)::value;
+        constexpr int KM = decltype(kmax)::value;
         T cur[NR];
 #pragma unroll
-        for (int k = 0; k < TD; ++k) {
+        for (int k = 0; k < KM; ++k) {
             // level k's plane q = j - k, rows [k, NR - k) valid
             T(&lv)[NR] = k == 0 ? pf[u % PF] : cur;
             T(&old)[NR] = acc[k][u];             // level k+1, plane q - 1
@@ -257,7 +269,23 @@ k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, int chunk, in
             }
         }
     };
-    for (int j = jstart; j <= jend; j += 3) wave_steps<0, 3>(j, jend, step);
+    // warm-up: steps jstart .. jstart + 2*TD - 1 (all exist: the chunk is not
+    // empty), level k from step 2k on
+    static_steps<0, 2 * TD>([&](auto st) __attribute__((always_inline)) {
+        constexpr int sidx = decltype(st)::value;
+        constexpr int km = sidx / 2 + 1 < TD ? sidx / 2 + 1 : TD;
+        step(jstart + sidx, std::integral_constant<int, sidx % 3>{}, std::integral_constant<int, km>{});
+    });
+    // then every level, three steps per iteration with the phases continuing
+    constexpr int P0 = (2 * TD) % 3;
+    const std::integral_constant<int, TD> all{};
+    for (int j = jstart + 2 * TD; j <= jend; j += 3) {
+        step(j, std::integral_constant<int, P0>{}, all);
+        if (j + 1 > jend) break;
+        step(j + 1, std::integral_constant<int, (P0 + 1) % 3>{}, all);
+        if (j + 2 > jend) break;
+        step(j + 2, std::integral_constant<int, (P0 + 2) % 3>{}, all);
+    }
     if (RES) residual_merge(rmax, residual);
 }
 
@@ -310,11 +338,11 @@ hipError_t run_star3d_wave(const SweepJob& j, int chunk, hipStream_t s) {
 
 // WPE: waves per SIMD asked of the register allocator (1 = no request)
 const Variant kStar3dWave[] = {
-    WSTAR(float, LOPE_F32, 4, 8, 4, 1, 1, 32),
-    WSTAR(float, LOPE_F32, 4, 10, 4, 1, 1, 32),
-    WSTAR(float, LOPE_F32, 4, 8, 2, 1, 1, 32),
-    WSTAR(float, LOPE_F32, 4, 6, 4, 1, 1, 32),
-    WSTAR(float, LOPE_F32, 4, 4, 4, 3, 1, 32),
+    WSTAR(float, LOPE_F32, 4, 8, 4, 1, 2, 32),
+    WSTAR(float, LOPE_F32, 4, 10, 4, 1, 2, 32),
+    WSTAR(float, LOPE_F32, 4, 8, 2, 1, 2, 32),
+    WSTAR(float, LOPE_F32, 4, 6, 4, 1, 2, 32),
+    WSTAR(float, LOPE_F32, 4, 4, 4, 3, 2, 32),
 };
 
 }  // namespace
