@@ -102,6 +102,30 @@ def test_every_variant_and_depth_agrees(ndim, r, shape_kind, dtype):
         np.testing.assert_array_equal(x.numpy(), ref)
 
 
+@pytest.mark.parametrize("shape", [(3, 5, 7), (9, 2, 130), (1, 17, 57), (40, 9, 56), (6, 33, 113)])
+def test_wave_brick_kernels_edge_shapes(shape):
+    """The wave-brick 3D kernels on grids narrower than one brick, thinner than
+    one row segment, shorter than one z-chunk or than the fused depth, and on
+    ragged multiples: every rule mix and chunk, against one sweep per pass
+    (bitwise) and the oracle."""
+    rng = np.random.default_rng([synth.CFG_TEST, 120 + shape[2]])
+    st = synth.contractive(synth.random_stencil(rng, 3, 1, "star"))
+    u = rng.uniform(-1, 1, size=shape).astype(np.float32)
+    n = 8                                   # two full passes of four sweeps
+    waves = [(vid, info) for vid, info in variants_for(3, 1, np.float32) if info.startswith("star3dw_")]
+    assert waves
+    for kinds in BCS[3] + [(D, D, P), (P, P, D)]:
+        want = oracle.iterate(u, st.coeffs, kinds, 0.5, n)
+        x, y = grid_from(u, 1), empty_grid(u.shape, 1, np.float32)
+        ref = (x, y)[L.lope_iterate(x, y, st, (kinds, 0.5), n, tdepth=1)].numpy()
+        assert rel_err(ref, want) <= tol(np.float32) * n
+        for vid, info in waves:
+            for chunk in (0, 1, 3):
+                a, b = grid_from(u, 1), empty_grid(u.shape, 1, np.float32)
+                idx = L.lope_iterate_tuned(a, b, st, (kinds, 0.5), n, variant=vid, chunk=chunk)
+                np.testing.assert_array_equal((a, b)[idx].numpy(), ref, err_msg="%s chunk %d %s" % (info, chunk, kinds))
+
+
 @pytest.mark.parametrize("n_steps", [0, 1, 2, 5, 8])
 def test_iterate_result_index_and_auto_depth(n_steps):
     u = _field((21, 40, 66), np.float32, 4)
