@@ -74,6 +74,13 @@ int check_grid(const lope_grid* g, const char* name) {
         }
     }
     if (g->stride[0] != 1) return fail(LOPE_ERR_INVALID_ARG, "%s: stride[0] must be 1", name);
+    // the padded box's element offsets must stay far from int64 overflow
+    // (2^50 elements per axis span: 4 PiB of float32)
+    for (int a = 0; a < g->ndim; ++a) {
+        const int64_t ext = g->n[a] + halo_lo(g, a) + halo_hi(g, a);
+        if (g->stride[a] > 0 && ext > ((int64_t)1 << 50) / g->stride[a])
+            return fail(LOPE_ERR_INVALID_ARG, "%s: axis %d spans more than 2^50 elements", name, a);
+    }
     const int64_t wx = halo_lo(g, 0) + halo_hi(g, 0), wy = halo_lo(g, 1) + halo_hi(g, 1);
     if (g->ndim >= 2 && g->stride[1] < g->n[0] + wx)
         return fail(LOPE_ERR_INVALID_ARG, "%s: stride[1]=%lld < n[0] plus the x halo", name, (long long)g->stride[1]);

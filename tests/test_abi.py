@@ -132,6 +132,9 @@ def test_invalid_arguments():
     assert apply(g, grid(ndim=2, origin=far()), s2, bc()) == E
     s5, _k5 = stencil(r=5)
     assert apply(grid(h=5), grid(h=5, origin=far()), s5, bc()) == E       # radius > 4
+    huge = grid(n=(8, 8, 1 << 10), sz=1 << 45)                             # z span beyond 2^50 elements
+    assert apply(huge, grid(n=(8, 8, 1 << 10), origin=far()), s, bc()) == E
+    assert "2^50" in L.lope_last_error().decode()
     idx = ctypes.c_int32()
     assert L.lope_iterate(ctypes.byref(grid()), ctypes.byref(grid(origin=far())), ctypes.byref(s),
                           ctypes.byref(bc()), -1, 0, None, ctypes.byref(idx)) == E
