@@ -253,9 +253,11 @@ typedef struct lope_stages {
 int lope_apply_stages(const lope_grid* src, const lope_grid* dst, const lope_stages* sg,
                       const lope_bc* bc, void* stream);
 
-/* n_steps two-stage steps alternating between a and b, one pass over memory
- * per step; *result_index = n_steps mod 2 (0: the state is in a).  Both grids'
- * halos must cover the first stencil's reach.  result_index must not be NULL. */
+/* n_steps two-stage steps alternating between a and b: two steps per pass
+ * over memory where a fused kernel takes both stencils (3D radius-1 stars,
+ * float32), else one; *result_index says which buffer holds the state (0: a;
+ * the parity of the number of passes).  Both grids' halos must cover the
+ * first stencil's reach.  result_index must not be NULL. */
 int lope_iterate_stages(const lope_grid* a, const lope_grid* b, const lope_stages* sg,
                         const lope_bc* bc, int64_t n_steps, void* stream, int32_t* result_index);
 

@@ -748,9 +748,11 @@ int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stenci
 
 namespace {
 
-// Two-stage steps: validation, then one pass per step with a fused two-level
-// variant (the tuned depth-2 choice for the first stencil if it can also take
-// the second, else the first that can) or the one-thread-per-point kernel.
+// Two-stage steps: validation, then passes of two steps with a fused
+// four-level variant while two or more steps remain, the rest one per pass
+// with a fused two-level variant (each the tuned choice of its depth for the
+// first stencil if it can also take the second, else the first that can) or
+// the one-thread-per-point kernel.
 int stages_impl(const lope_grid* a, const lope_grid* b, const lope_stages* sg, const lope_bc* bc, int64_t n_steps,
                 void* stream, int32_t* result_index) {
     if (!result_index) return fail(LOPE_ERR_INVALID_ARG, "null result_index");
@@ -774,29 +776,43 @@ int stages_impl(const lope_grid* a, const lope_grid* b, const lope_stages* sg, c
     if ((rc = check_memory(a, "a")) || (rc = check_memory(b, "b"))) return rc;
     if (is_empty(a) || n_steps == 0) return LOPE_OK;
     auto& R = registry().v;
-    auto takes = [&](int v) {
-        return v > 0 && R[v - 1].sfn && variant_fits(R[v - 1], sj.s1, 2) && variant_fits(R[v - 1], sj.s2, 2);
+    // a variant making depth / 2 steps per pass that takes both stencils
+    auto takes = [&](int v, int depth) {
+        return v > 0 && R[v - 1].sfn && variant_fits(R[v - 1], sj.s1, depth) && variant_fits(R[v - 1], sj.s2, depth);
     };
-    int chunk = 0, variant = 0;
-    {
-        const Plan p = choose(sj.s1, 2, 0, 0);
-        if (p.tdepth == 2 && takes(p.variant)) {
-            variant = p.variant;
-            chunk = p.chunk;
+    // the tuned choice for that depth if it takes both, else the first that does
+    auto pick = [&](int depth, int* chunk) {
+        *chunk = 0;
+        const Plan p = choose(sj.s1, depth, 0, 0);
+        if (p.tdepth == depth && takes(p.variant, depth)) {
+            *chunk = p.chunk;
+            return p.variant;
         }
-    }
-    for (size_t i = 0; !variant && i < R.size(); ++i)
-        if (takes((int)i + 1)) variant = (int)i + 1;
+        for (size_t i = 0; i < R.size(); ++i)
+            if (takes((int)i + 1, depth)) return (int)i + 1;
+        return 0;
+    };
+    int chunk2 = 0, chunk1 = 0;
+    const int v2 = pick(4, &chunk2);   // two steps per pass
+    const int v1 = pick(2, &chunk1);   // one step per pass
     const DevGrid ga = dev_grid(a), gb = dev_grid(b);
     const hipStream_t s = (hipStream_t)stream;
-    for (int64_t t = 0; t < n_steps; ++t) {
-        sj.s1.src = (t & 1) ? gb : ga;
-        sj.s1.dst = (t & 1) ? ga : gb;
-        const hipError_t e = variant ? R[variant - 1].sfn(sj, chunk > 0 ? chunk : R[variant - 1].default_chunk, s)
-                                     : launch_stages_generic(sj, s);
+    int64_t done = 0, passes = 0;
+    while (done < n_steps) {
+        sj.s1.src = (passes & 1) ? gb : ga;
+        sj.s1.dst = (passes & 1) ? ga : gb;
+        hipError_t e;
+        if (v2 && n_steps - done >= 2) {
+            e = R[v2 - 1].sfn(sj, chunk2 > 0 ? chunk2 : R[v2 - 1].default_chunk, s);
+            done += 2;
+        } else {
+            e = v1 ? R[v1 - 1].sfn(sj, chunk1 > 0 ? chunk1 : R[v1 - 1].default_chunk, s) : launch_stages_generic(sj, s);
+            done += 1;
+        }
         if (e != hipSuccess) return hip_fail(e, "two-stage launch");
+        ++passes;
     }
-    *result_index = (int32_t)(n_steps & 1);
+    *result_index = (int32_t)(passes & 1);
     return LOPE_OK;
 }
 

@@ -117,14 +117,18 @@ __device__ __forceinline__ void static_steps(F&& f) {
 
 // RES: also merge max |u_TD - u_(TD-1)| over the stored outputs (the change
 // made by the last sweep) into the device double `residual`.
-template <typename T, int TD, int P, int NW, bool DXY, bool DZ, bool RES, int PF, int WPE>
+// STG: 0 = TD sweeps of one stencil; 1, 2 = TD / 2 two-stage steps: odd
+// levels apply cf, even levels cf2 (plus alpha times the state two levels
+// below, the state at the start of the step, when STG = 2).
+template <typename T, int TD, int P, int NW, bool DXY, bool DZ, bool RES, int STG, int PF, int WPE>
 __global__ void __launch_bounds__(NW * 64, WPE)
-k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, int chunk, int strips, int segs, int nwaves,
-              int nblocks_padded, double* residual) {
+k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, Coef7<T> cf2, T alpha, int chunk, int strips,
+              int segs, int nwaves, int nblocks_padded, double* residual) {
     static_assert(PF == 1 || PF == 3, "the march is unrolled by three");
     // float64 would need two DPP moves per lane shift (no DPP form of the
     // 64-bit fma) and twice the registers: the LDS designs serve it better
     static_assert(std::is_same<T, float>::value, "float32 only");
+    static_assert(STG == 0 || (TD % 2 == 0 && !RES), "two-stage steps pair the levels");
     typedef typename WMask<T>::type M;
     constexpr int G = TD;
     constexpr int NR = P + 2 * G;
@@ -206,6 +210,7 @@ k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, int chunk, in
         constexpr int u = decltype(phase)::value;
         constexpr int KM = decltype(kmax)::value;
         T cur[NR];
+        T base[NR];   // STG = 2: the state at the start of the step (level k-1 for an even level k+1)
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             // level k's plane q = j - k, rows [k, NR - k) valid
@@ -216,26 +221,38 @@ k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, int chunk, in
             T nxt[NR], bl[NR];
 #pragma unroll
             for (int r = k; r < NR - k; ++r) bl[r] = k == 0 && DXY ? wblend(live, lv[r], g) : lv[r];
+            // the stencil of level k+1 (STG: the second one on even levels)
+            const bool second = STG != 0 && (k % 2) == 1;
+            const Coef7<T>& c = second ? cf2 : cf;
+            // STG = 2: an even level starts each plane from alpha times the
+            // state at the start of the step (same plane, row), then the taps
+            const bool with_alpha = STG == 2 && second;
+            if (STG == 2 && !second) {
+#pragma unroll
+                for (int r = k; r < NR - k; ++r) base[r] = bl[r];
+            }
             // rows lo .. hi-1 of level k+1: y-1 tap, x taps (three rows at a
             // time), y+1 tap; then the z+1 tap finishes plane q-1 and the z-1
             // tap starts plane q+1
             const int lo = k + 1, hi = NR - 1 - k;
 #pragma unroll
-            for (int r = lo; r < hi; ++r) mid[r] = fma(cf.c[1], bl[r - 1], mid[r]);
+            for (int r = lo; r < hi; ++r) mid[r] = fma(c.c[1], bl[r - 1], mid[r]);
 #pragma unroll
             for (int r = lo; r < hi; r += 3) {
                 if (r + 3 <= hi)
-                    fma_xrows(mid[r], mid[r + 1], mid[r + 2], bl[r], bl[r + 1], bl[r + 2], cf.c[2], cf.c[3], cf.c[4]);
+                    fma_xrows(mid[r], mid[r + 1], mid[r + 2], bl[r], bl[r + 1], bl[r + 2], c.c[2], c.c[3], c.c[4]);
                 else if (r + 2 == hi)
-                    fma_xrows(mid[r], mid[r + 1], bl[r], bl[r + 1], cf.c[2], cf.c[3], cf.c[4]);
+                    fma_xrows(mid[r], mid[r + 1], bl[r], bl[r + 1], c.c[2], c.c[3], c.c[4]);
                 else
-                    fma_xrows(mid[r], bl[r], cf.c[2], cf.c[3], cf.c[4]);
+                    fma_xrows(mid[r], bl[r], c.c[2], c.c[3], c.c[4]);
             }
 #pragma unroll
             for (int r = lo; r < hi; ++r) {
-                mid[r] = fma(cf.c[5], bl[r + 1], mid[r]);
-                nxt[r] = fma(cf.c[6], bl[r], old[r]);
-                nw[r] = cf.c[0] * bl[r];
+                mid[r] = fma(c.c[5], bl[r + 1], mid[r]);
+                nxt[r] = fma(c.c[6], bl[r], old[r]);
+                // plane q+1 of level k+1 at row r; with alpha its start is
+                // alpha * (that plane of level k-1), completed this step
+                nw[r] = with_alpha ? fma(c.c[0], bl[r], alpha * base[r]) : c.c[0] * bl[r];
             }
             if (k == 0) load_plane(min(j + PF, jend), pf[u % PF]);
             // the rule on the completed plane p of level k+1
@@ -289,8 +306,8 @@ k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, int chunk, in
     if (RES) residual_merge(rmax, residual);
 }
 
-template <typename T, int TD, int P, int NW, int PF, int WPE>
-hipError_t run_star3d_wave(const SweepJob& j, int chunk, hipStream_t s) {
+template <typename T>
+Coef7<T> coef7(const SweepJob& j) {
     Coef7<T> cf;
     auto dense = [&](int ox, int oy, int oz) { return (T)j.dense[(ox + 1) + (oy + 1) * 3 + (oz + 1) * 9]; };
     cf.c[0] = dense(0, 0, -1);
@@ -300,6 +317,13 @@ hipError_t run_star3d_wave(const SweepJob& j, int chunk, hipStream_t s) {
     cf.c[4] = dense(1, 0, 0);
     cf.c[5] = dense(0, 1, 0);
     cf.c[6] = dense(0, 0, 1);
+    return cf;
+}
+
+// One pass over j's grids (its rule and residual; the stencils in cf, cf2).
+template <typename T, int TD, int P, int NW, int PF, int WPE, int STG>
+hipError_t launch_wave3(const SweepJob& j, const Coef7<T>& cf, const Coef7<T>& cf2, T alpha, int chunk,
+                        hipStream_t s) {
     if (chunk <= 0) chunk = 64;
     const int out_cols = 64 - 2 * TD;
     const int strips = (j.src.nx + out_cols - 1) / out_cols;
@@ -311,8 +335,8 @@ hipError_t run_star3d_wave(const SweepJob& j, int chunk, hipStream_t s) {
     const int nbp = padded_block_count((nw + NW - 1) / NW);
     const bool dxy = !j.rule.per[0] || !j.rule.per[1], dz = !j.rule.per[2];
 #define LOPE_WAVE3_LAUNCH(A, B, C)                                                                              \
-    hipLaunchKernelGGL((k_star3d_wave<T, TD, P, NW, A, B, C, PF, WPE>), dim3(nbp), dim3(NW * 64), 0, s, j.src,   \
-                       j.dst, j.rule, cf, chunk, strips, segs, nw, nbp, j.residual)
+    hipLaunchKernelGGL((k_star3d_wave<T, TD, P, NW, A, B, C, STG, PF, WPE>), dim3(nbp), dim3(NW * 64), 0, s,    \
+                       j.src, j.dst, j.rule, cf, cf2, alpha, chunk, strips, segs, nw, nbp, j.residual)
 #define LOPE_WAVE3_RULE(C)                 \
     if (dxy && dz)                         \
         LOPE_WAVE3_LAUNCH(true, true, C);  \
@@ -322,8 +346,8 @@ hipError_t run_star3d_wave(const SweepJob& j, int chunk, hipStream_t s) {
         LOPE_WAVE3_LAUNCH(false, true, C); \
     else                                   \
         LOPE_WAVE3_LAUNCH(false, false, C)
-    if (j.residual) {
-        LOPE_WAVE3_RULE(true);
+    if (STG == 0 && j.residual) {
+        LOPE_WAVE3_RULE(STG == 0);
     } else {
         LOPE_WAVE3_RULE(false);
     }
@@ -332,9 +356,25 @@ hipError_t run_star3d_wave(const SweepJob& j, int chunk, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T, int TD, int P, int NW, int PF, int WPE>
+hipError_t run_star3d_wave(const SweepJob& j, int chunk, hipStream_t s) {
+    const Coef7<T> cf = coef7<T>(j);
+    return launch_wave3<T, TD, P, NW, PF, WPE, 0>(j, cf, cf, (T)0, chunk, s);
+}
+
+// TD / 2 two-stage steps per pass (levels 1, 3, .. the first stencil; levels
+// 2, 4, .. the second, plus alpha times the state at the start of the step)
+template <typename T, int TD, int P, int NW, int PF, int WPE>
+hipError_t run_star3d_wave_stages(const StageJob& sj, int chunk, hipStream_t s) {
+    const Coef7<T> cf = coef7<T>(sj.s1), cf2 = coef7<T>(sj.s2);
+    if (sj.alpha != 0.0) return launch_wave3<T, TD, P, NW, PF, WPE, 2>(sj.s1, cf, cf2, (T)sj.alpha, chunk, s);
+    return launch_wave3<T, TD, P, NW, PF, WPE, 1>(sj.s1, cf, cf2, (T)0, chunk, s);
+}
+
 #define WSTAR(T, DT, TD, P, NW, PF, WPE, CH)                                                                \
     {"star3dw_" #T "_r1_t" #TD "_p" #P "_pf" #PF "_nw" #NW "_w" #WPE, FAM_STAR3D_WAVE, 3, 1, TD, DT, 0,       \
-     64 - 2 * (TD), P, (NW) * 64, CH, &run_star3d_wave<T, TD, P, NW, PF, WPE>, 1, nullptr}
+     64 - 2 * (TD), P, (NW) * 64, CH, &run_star3d_wave<T, TD, P, NW, PF, WPE>, 1,                           \
+     &run_star3d_wave_stages<T, TD, P, NW, PF, WPE>}
 
 // WPE: waves per SIMD asked of the register allocator (1 = no request)
 const Variant kStar3dWave[] = {

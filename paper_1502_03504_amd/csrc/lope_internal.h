@@ -95,7 +95,7 @@ struct Variant {
     int default_chunk;
     VariantFn fn;
     int res;                        // 1: honours SweepJob::residual
-    StageFn sfn;                    // two-stage step in one pass (tdepth 2 kernels), or null
+    StageFn sfn;                    // tdepth / 2 two-stage steps in one pass, or null
 };
 
 // Registries filled by each kernel file.

@@ -60,6 +60,38 @@ def test_matches_oracle_and_composition(case, alpha, dtype):
         np.testing.assert_array_equal(got, a.numpy())
 
 
+@pytest.mark.parametrize("kinds", [(P, P, P), (D, D, P), (P, D, D)])
+def test_two_steps_per_pass_each_wave_kernel(kinds):
+    """Every wave-brick variant, chosen through the tuning table, makes two
+    steps per pass: against the oracle, and with alpha = 0 bitwise equal to
+    two sweeps per step."""
+    from tests.gpu_util import variants_for
+    rng = np.random.default_rng([synth.CFG_TEST, 985])
+    c1 = synth.contractive(synth.random_stencil(rng, 3, 1, "star")).coeffs
+    c2 = synth.contractive(synth.random_stencil(rng, 3, 1, "star")).coeffs * 0.5
+    s1, s2 = synth.Stencil(3, 1, c1), synth.Stencil(3, 1, c2)
+    u = rng.uniform(0, 1, (13, 22, 70)).astype(np.float32)
+    bc = (kinds, 0.4)
+    n = 5                                           # two passes of two steps, one of one
+    waves = [(vid, info) for vid, info in variants_for(3, 1, np.float32) if info.startswith("star3dw_")]
+    assert waves
+    want = oracle.stages_iterate(u, c1, c2, 0.45, kinds, 0.4, n)
+    a, b = grid_from(u, 1), empty_grid(u.shape, 1, np.float32)
+    for _ in range(n):
+        L.lope_apply(a, b, s1, bc)
+        L.lope_apply(b, a, s2, bc)
+    composed = a.numpy()
+    probe = grid_from(u, 1)
+    try:
+        for vid, info in waves:
+            L.lope_tune_set(probe, s1, vid, 4)
+            got = _run(u, s1, s2, 0.45, bc, n).numpy()
+            assert rel_err(got, want) <= TOL[np.float32] * 2 * n, info
+            np.testing.assert_array_equal(_run(u, s1, s2, 0.0, bc, n).numpy(), composed, err_msg=info)
+    finally:
+        L.lope_tune_set(probe, s1, 0, 4)
+
+
 def test_first_stencil_reach_sets_the_halo():
     """The intermediate's halo comes from the rule, so only the first
     stencil's reach is checked against the grid."""
