@@ -91,6 +91,9 @@ const Variant kPlane2dWave[] = {
     PWAVE(float, LOPE_F32, 2, true, 4, 128),
     PWAVE(float, LOPE_F32, 3, true, 4, 128),
     PWAVE(float, LOPE_F32, 4, true, 4, 128),
+    PWAVE(float, LOPE_F32, 5, true, 4, 128),
+    PWAVE(float, LOPE_F32, 6, true, 4, 128),
+    PWAVE(float, LOPE_F32, 8, true, 4, 128),
     PWAVE(float, LOPE_F32, 1, false, 4, 128),
     PWAVE(float, LOPE_F32, 2, false, 4, 128),
     PWAVE(float, LOPE_F32, 3, false, 4, 128),
@@ -98,6 +101,8 @@ const Variant kPlane2dWave[] = {
     PWAVE(double, LOPE_F64, 1, false, 4, 32),
     PWAVE(double, LOPE_F64, 2, false, 4, 32),
     PWAVE(double, LOPE_F64, 4, false, 4, 32),
+    PWAVE(double, LOPE_F64, 6, false, 4, 32),
+    PWAVE(double, LOPE_F64, 8, false, 4, 32),
     PWAVE(double, LOPE_F64, 2, true, 4, 32),
 };
 

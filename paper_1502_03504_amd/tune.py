@@ -23,6 +23,7 @@ from ._lib import check, load
 
 ARCH = "gfx950"
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+MAX_REQUEST = 4   # the deepest tdepth a caller can request of lope_iterate
 
 
 def _variant_table():
@@ -111,10 +112,13 @@ def autotune(a, b, stencil, bc, sweeps=24, chunks=(0, 16, 32, 64, 128), tdepths=
         return None, results
     best = min(results, key=lambda r: r["s_per_sweep"])
     # the overall best answers automatic requests (0); the best of each depth
-    # answers explicit requests for that depth
+    # answers explicit requests for that depth (requests go up to MAX_REQUEST;
+    # deeper variants serve automatic requests only)
     choices = {0: best}
     for r in results:
         d = r["tdepth"]
+        if d > MAX_REQUEST:
+            continue
         if d not in choices or r["s_per_sweep"] < choices[d]["s_per_sweep"]:
             choices[d] = r
     if register:
