@@ -178,7 +178,8 @@ int lope_apply(const lope_grid* src, const lope_grid* dst, const lope_stencil* s
 /* n_steps sweeps alternating between a and b (section 3.2, the loop around
  * the sweep and the halo transfer; double buffering per section 2.2).  The
  * initial state is a's interior.  Several sweeps may be fused per pass over
- * memory (tdepth, 0 = automatic); the result is identical.  *result_index is
+ * memory: tdepth 1..4 asks for that many, 0 lets the tuning table choose
+ * (possibly more than 4); the result is identical.  *result_index is
  * set to 0 if the final state is in a, 1 if in b (n_steps mod 2 when one
  * sweep runs per pass).  Both grids' halos must cover the stencil's reach.
  * result_index must not be NULL. */
