@@ -148,7 +148,7 @@ def measure_batch(reps=3, per_grid=True):
         return ts[len(ts) // 2]
 
     by_depth = {}
-    for td in (1, 2, 3, 4):
+    for td in (1, 2, 3, 4, 5, 6, 7, 8):
         plan.set_depth(td)
         by_depth[td] = timed(plan.apply)
     best = min(by_depth, key=by_depth.get)

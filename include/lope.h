@@ -331,7 +331,7 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream);
  * grid per sweep (the baseline the batched launch is compared with). */
 int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream);
 
-/* Sweeps fused per launch (1..4, default 2): passes of tdepth sweeps, the
+/* Sweeps fused per launch (1..8, default 2): passes of tdepth sweeps, the
  * remainder of n_steps in one shorter pass.  Builds the plan's tile table for
  * the depth if needed (synchronous upload). */
 int lope_batch_plan_set_depth(lope_batch_plan* plan, int32_t tdepth);

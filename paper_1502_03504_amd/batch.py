@@ -41,7 +41,7 @@ class BatchPlan:
         check(load().lope_batch_apply_per_grid(self.handle, self._stream(stream)))
 
     def set_depth(self, tdepth: int) -> None:
-        """Sweeps fused per launch (1..4)."""
+        """Sweeps fused per launch (1..8)."""
         check(load().lope_batch_plan_set_depth(self.handle, int(tdepth)))
 
     def result_index(self) -> int:

@@ -527,8 +527,8 @@ struct lope_batch_plan {
     std::vector<SweepJob> jobs;       // per-grid launches (the comparison path)
     std::vector<int> job_variant;
     BatchGrid* d_grids = nullptr;
-    BatchItem* d_items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // tile tables per depth
-    int nitems[5] = {0, 0, 0, 0, 0};
+    BatchItem* d_items[kBatchMaxDepth + 1] = {};   // tile tables per depth
+    int nitems[kBatchMaxDepth + 1] = {};
     hipGraphExec_t graph = nullptr;   // every pass of lope_batch_apply, recorded for graph_depth
     int graph_depth = 0;
 };
@@ -539,7 +539,7 @@ void plan_free(lope_batch_plan* p) {
     if (!p) return;
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
     if (p->d_grids) (void)hipFree(p->d_grids);
-    for (int d = 0; d < 5; ++d)
+    for (int d = 0; d <= kBatchMaxDepth; ++d)
         if (p->d_items[d]) (void)hipFree(p->d_items[d]);
     delete p;
 }
@@ -1084,7 +1084,8 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
 
 int lope_batch_plan_set_depth(lope_batch_plan* plan, int32_t tdepth) {
     if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
-    if (tdepth < 1 || tdepth > 4) return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 1..4", tdepth);
+    if (tdepth < 1 || tdepth > kBatchMaxDepth)
+        return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 1..%d", tdepth, kBatchMaxDepth);
     int rc;
     if ((rc = device_ready())) return rc;
     plan->tdepth = tdepth;

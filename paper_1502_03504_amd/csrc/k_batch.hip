@@ -76,6 +76,10 @@ hipError_t launch_batch_pass(const BatchGrid* grids, const BatchItem* items, int
             case 2: launch_td<float, 2>(grids, items, nitems, parity, s); break;
             case 3: launch_td<float, 3>(grids, items, nitems, parity, s); break;
             case 4: launch_td<float, 4>(grids, items, nitems, parity, s); break;
+            case 5: launch_td<float, 5>(grids, items, nitems, parity, s); break;
+            case 6: launch_td<float, 6>(grids, items, nitems, parity, s); break;
+            case 7: launch_td<float, 7>(grids, items, nitems, parity, s); break;
+            case 8: launch_td<float, 8>(grids, items, nitems, parity, s); break;
             default: return hipErrorInvalidValue;
         }
     } else {
@@ -84,6 +88,10 @@ hipError_t launch_batch_pass(const BatchGrid* grids, const BatchItem* items, int
             case 2: launch_td<double, 2>(grids, items, nitems, parity, s); break;
             case 3: launch_td<double, 3>(grids, items, nitems, parity, s); break;
             case 4: launch_td<double, 4>(grids, items, nitems, parity, s); break;
+            case 5: launch_td<double, 5>(grids, items, nitems, parity, s); break;
+            case 6: launch_td<double, 6>(grids, items, nitems, parity, s); break;
+            case 7: launch_td<double, 7>(grids, items, nitems, parity, s); break;
+            case 8: launch_td<double, 8>(grids, items, nitems, parity, s); break;
             default: return hipErrorInvalidValue;
         }
     }

@@ -380,9 +380,7 @@ hipError_t run_star3d_wave_stages(const StageJob& sj, int chunk, hipStream_t s) 
 const Variant kStar3dWave[] = {
     WSTAR(float, LOPE_F32, 4, 8, 4, 1, 2, 32),
     WSTAR(float, LOPE_F32, 4, 10, 4, 1, 2, 32),
-    WSTAR(float, LOPE_F32, 4, 8, 2, 1, 2, 32),
     WSTAR(float, LOPE_F32, 4, 6, 4, 1, 2, 32),
-    WSTAR(float, LOPE_F32, 4, 4, 4, 3, 2, 32),
 };
 
 }  // namespace

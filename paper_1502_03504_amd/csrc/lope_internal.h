@@ -135,6 +135,8 @@ struct BatchItem {
     int32_t x0, y0, y1;
 };
 
+// Sweeps per batch pass: 1 .. kBatchMaxDepth.
+constexpr int kBatchMaxDepth = 8;
 // Output columns of a batch strip sweeping tdepth times per pass.
 int batch_strip_width(int tdepth);
 // One pass of tdepth sweeps over every listed tile; parity 0 reads src, 1 reads dst.

@@ -279,7 +279,7 @@ def test_batch_matches_per_grid_and_oracle(dtype):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
-    """Batched launches (every tile of every grid per launch, 1..4 sweeps
+    """Batched launches (every tile of every grid per launch, 1..8 sweeps
     fused) against the oracle and, value for value, against one launch per
     grid per sweep."""
     rng = np.random.default_rng([synth.CFG_TEST, 401])
@@ -287,7 +287,7 @@ def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
     entries, fields = _batch_entries(rng, 24, dtype, lo=3, hi=700)
     plan = L.BatchPlan(entries, n)
     ref = None
-    for depth in (2, 1, 3, 4):
+    for depth in (2, 1, 3, 4, 5, 6, 7, 8):
         for (src, _, _, _), u in zip(entries, fields):
             src.interior().copy_(torch.from_numpy(u).cuda())
         plan.set_depth(depth)
