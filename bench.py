@@ -212,7 +212,7 @@ def measure_workloads(reps=3):
         b = a.empty_like()
         pts, esize = int(case.field.size), case.field.dtype.itemsize
         case = case._replace(field=None)
-        vid = L.lope_select_variant(a, case.stencil, 0)
+        vid = L.lope_select_variant(a, case.stencil, 0, bc=case.bc)
         info = L.lope_variant_info(vid) if vid > 0 else "generic"
         L.lope_iterate(a, b, case.stencil, case.bc, case.steps)
         ts = []
@@ -280,7 +280,7 @@ def main():
     st = synth.heat_star(3, 0.125)
     bc = synth.Boundary(("periodic",) * 3, 0.0)
 
-    vid = args.variant or L.lope_select_variant(a, st, args.tdepth)
+    vid = args.variant or L.lope_select_variant(a, st, args.tdepth, bc=bc)
     info = L.lope_variant_info(vid) if vid > 0 else "generic"
     td = int(dict(kv.split("=") for kv in info.split()[1:]).get("tdepth", 1)) if vid > 0 else 1
     log("kernel:", info)

@@ -146,7 +146,9 @@ typedef struct lope_tuning {
                                      LOPE_VARIANT_GENERIC = the one-thread-per-point kernel */
     int32_t tdepth;               /* sweeps fused per pass, 1..4; 0 = automatic */
     int32_t chunk;                /* extent of the marched axis per workgroup; 0 = automatic */
-    int32_t reserved;
+    int32_t rules;                /* lope_tune_set: the boundary-rule class the choice is for,
+                                     0 = periodic on every axis, 1 = some axis Dirichlet;
+                                     ignored by lope_iterate_tuned */
 } lope_tuning;
 
 /* ---- device ------------------------------------------------------------ */
@@ -359,15 +361,17 @@ int lope_variant_count(void);
 int lope_variant_info(int id, char* text, int cap);
 
 /* Id of the kernel variant lope_iterate would use for one pass with tdepth
- * sweeps (0 = automatic) on this grid/stencil, or a negative status. */
-int lope_select_variant(const lope_grid* g, const lope_stencil* st, int32_t tdepth);
+ * sweeps (0 = automatic) on this grid/stencil and rule (NULL: periodic on
+ * every axis), or a negative status. */
+int lope_select_variant(const lope_grid* g, const lope_stencil* st, const lope_bc* bc, int32_t tdepth);
 
 /* Register a launch choice for grids and stencils like (g, st): use
  * tune->variant and tune->chunk.  tune->tdepth says which request it answers:
  * 0 = lope_iterate with tdepth 0 (automatic), k = lope_iterate with tdepth k
  * (then the variant's own depth must be k).  The key is (ndim, radius,
  * dtype, star/box shape, size bucket = floor(log2(interior points)),
- * requested depth).  tune->variant = 0 removes the choice registered for that
+ * requested depth, rule class tune->rules).  tune->variant = 0 removes the
+ * choice registered for that
  * request (tdepth 0..4), so the request falls back to the default variant.
  * Only structural checks are made (no device access). */
 int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning* tune);

@@ -382,16 +382,27 @@ def variants():
     return [lope_variant_info(i) for i in range(1, lope_variant_count() + 1)]
 
 
-def lope_select_variant(grid: Grid, stencil, tdepth: int = 0) -> int:
+def lope_select_variant(grid: Grid, stencil, tdepth: int = 0, bc=None) -> int:
+    """The variant lope_iterate would use (bc None: periodic on every axis)."""
     s = _Stencil(stencil)
     g = grid.descriptor()
-    return check(load().lope_select_variant(_ref(g), _ref(s.c), int(tdepth)))
+    b = _bc(bc, grid.ndim) if bc is not None else None
+    return check(load().lope_select_variant(_ref(g), _ref(s.c), _ref(b) if b is not None else None, int(tdepth)))
 
 
-def lope_tune_set(grid: Grid, stencil, variant: int, tdepth: int = 0, chunk: int = 0) -> None:
+def rule_class(bc, ndim: int) -> int:
+    """The tuning table's boundary-rule class: 1 if some axis is Dirichlet."""
+    b = _bc(bc, ndim)
+    return int(any(b.kind[a] == _lib.LOPE_BC_DIRICHLET for a in range(ndim)))
+
+
+def lope_tune_set(grid: Grid, stencil, variant: int, tdepth: int = 0, chunk: int = 0, bc=None) -> None:
+    """Register a choice for grids, stencils and rules like these (bc None:
+    periodic on every axis); variant 0 removes it."""
     s = _Stencil(stencil)
     g = grid.descriptor()
-    t = _lib.lope_tuning(int(variant), int(tdepth), int(chunk), 0)
+    rules = rule_class(bc, grid.ndim) if bc is not None else 0
+    t = _lib.lope_tuning(int(variant), int(tdepth), int(chunk), rules)
     check(load().lope_tune_set(_ref(g), _ref(s.c), _ref(t)))
 
 

@@ -64,7 +64,7 @@ class lope_tuning(ctypes.Structure):
         ("variant", ctypes.c_int32),
         ("tdepth", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("rules", ctypes.c_int32),
     ]
 
 
@@ -123,7 +123,7 @@ SIGNATURES = {
     "lope_last_error": (ctypes.c_char_p, []),
     "lope_variant_count": (ctypes.c_int, []),
     "lope_variant_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, ctypes.c_int]),
-    "lope_select_variant": (ctypes.c_int, [P(lope_grid), P(lope_stencil), ctypes.c_int32]),
+    "lope_select_variant": (ctypes.c_int, [P(lope_grid), P(lope_stencil), P(lope_bc), ctypes.c_int32]),
     "lope_tune_set": (ctypes.c_int, [P(lope_grid), P(lope_stencil), P(lope_tuning)]),
 }
 

@@ -334,14 +334,23 @@ struct TuneChoice {
     int variant, tdepth, chunk;
 };
 std::mutex g_tune_mu;
-typedef std::tuple<int, int, int, int, int, int> TuneKey;
+typedef std::tuple<int, int, int, int, int, int, int> TuneKey;
 std::map<TuneKey, TuneChoice> g_tune;
 
-// (ndim, radius, dtype, star, floor(log2 points), requested sweeps per pass; 0 = automatic)
-TuneKey tune_key(int ndim, int radius, int dtype, bool star, int64_t points, int tdepth_req) {
+// (ndim, radius, dtype, star, floor(log2 points), requested sweeps per pass (0 = automatic),
+// rule class: 0 = periodic on every axis, 1 = some axis Dirichlet)
+// The tuning table's rule class of a job: 1 if some axis is Dirichlet (kernels
+// that bit-blend the boundary value run differently from all-periodic ones).
+int rule_class(const SweepJob& j) {
+    for (int a = 0; a < j.ndim; ++a)
+        if (!j.rule.per[a]) return 1;
+    return 0;
+}
+
+TuneKey tune_key(int ndim, int radius, int dtype, bool star, int64_t points, int tdepth_req, int rules) {
     int bucket = 0;
     while (bucket < 62 && ((int64_t)1 << (bucket + 1)) <= points) ++bucket;
-    return std::make_tuple(ndim, radius, dtype, star ? 1 : 0, bucket, tdepth_req);
+    return std::make_tuple(ndim, radius, dtype, star ? 1 : 0, bucket, tdepth_req, rules);
 }
 
 bool variant_fits(const Variant& v, const SweepJob& j, int tdepth) {
@@ -411,7 +420,7 @@ Plan choose(const SweepJob& j, int tdepth_req, int variant_req, int chunk_req) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const int64_t pts = (int64_t)j.src.nx * j.src.ny * j.src.nz;
-        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts, td > 0 ? td : 0));
+        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts, td > 0 ? td : 0, rule_class(j)));
         if (it != g_tune.end() && it->second.variant > 0 &&
             variant_fits(registry().v[it->second.variant - 1], j, it->second.tdepth)) {
             p.variant = it->second.variant;
@@ -442,7 +451,7 @@ int residual_variant(const SweepJob& j, int depth, int* chunk) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const int64_t pts = (int64_t)j.src.nx * j.src.ny * j.src.nz;
-        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts, depth));
+        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts, depth, rule_class(j)));
         if (it != g_tune.end() && it->second.variant > 0 && it->second.tdepth == depth) {
             const Variant& v = registry().v[it->second.variant - 1];
             if (v.res && variant_fits(v, j, depth)) {
@@ -1176,14 +1185,15 @@ int lope_variant_info(int id, char* text, int cap) {
     return LOPE_OK;
 }
 
-int lope_select_variant(const lope_grid* g, const lope_stencil* st, int32_t tdepth) {
+int lope_select_variant(const lope_grid* g, const lope_stencil* st, const lope_bc* bc, int32_t tdepth) {
     int rc;
     if ((rc = check_grid(g, "grid")) || (rc = check_stencil(st, g->ndim, nullptr))) return rc;
+    if (bc && (rc = check_bc(bc, g->ndim))) return rc;
     if (tdepth < 0 || tdepth > 4) return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 0..4", tdepth);
     static thread_local SweepJob job;
-    lope_bc bc{};
-    for (int a = 0; a < 3; ++a) bc.kind[a] = LOPE_BC_PERIODIC;
-    build_job(job, g, g, st, &bc, false);
+    lope_bc periodic{};
+    for (int a = 0; a < 3; ++a) periodic.kind[a] = LOPE_BC_PERIODIC;
+    build_job(job, g, g, st, bc ? bc : &periodic, false);
     return choose(job, tdepth, 0, 0).variant;
 }
 
@@ -1193,15 +1203,17 @@ int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning*
     if ((rc = check_grid(g, "grid")) || (rc = check_stencil(st, g->ndim, nullptr))) return rc;
     if (tune->variant < 0 || tune->variant > (int)registry().v.size())
         return fail(LOPE_ERR_INVALID_ARG, "variant %d out of range", tune->variant);
+    if (tune->rules != 0 && tune->rules != 1)
+        return fail(LOPE_ERR_INVALID_ARG, "rules %d: 0 (every axis periodic) or 1 (some axis Dirichlet)", tune->rules);
     static thread_local SweepJob job;
     lope_bc bc{};
-    for (int a = 0; a < 3; ++a) bc.kind[a] = LOPE_BC_PERIODIC;
+    for (int a = 0; a < 3; ++a) bc.kind[a] = tune->rules && a == 0 ? LOPE_BC_DIRICHLET : LOPE_BC_PERIODIC;
     build_job(job, g, g, st, &bc, false);
     if (tune->variant == 0) {   // remove the choice for this request
         if (tune->tdepth < 0 || tune->tdepth > 4) return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 0..4", tune->tdepth);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune.erase(tune_key(job.ndim, job.radius, job.dtype, job.star, (int64_t)job.src.nx * job.src.ny * job.src.nz,
-                              tune->tdepth));
+                              tune->tdepth, tune->rules));
         return LOPE_OK;
     }
     const int td = registry().v[tune->variant - 1].tdepth;
@@ -1211,7 +1223,7 @@ int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning*
         return fail(LOPE_ERR_INVALID_ARG, "tdepth %d: 0 (automatic) or the variant's own depth %d", tune->tdepth, td);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[tune_key(job.ndim, job.radius, job.dtype, job.star, (int64_t)job.src.nx * job.src.ny * job.src.nz,
-                    tune->tdepth)] = TuneChoice{tune->variant, td, tune->chunk};
+                    tune->tdepth, tune->rules)] = TuneChoice{tune->variant, td, tune->chunk};
     return LOPE_OK;
 }
 

@@ -5,8 +5,9 @@ candidate chunk length (the extent of the marched axis per workgroup), with
 HIP events on the current stream, and registers the fastest per-sweep choice
 in the library's table (lope_tune_set), which lope_iterate consults when its
 tdepth argument is 0.  Results are kept in a JSON cache keyed by
-(architecture, ndim, radius, dtype, star/box, size bucket = floor(log2 points))
-and by variant NAME, so a cache survives rebuilds that renumber variants.
+(architecture, ndim, radius, dtype, star/box, size bucket = floor(log2 points),
+requested depth, boundary-rule class) and by variant NAME, so a cache
+survives rebuilds that renumber variants.
 Tuning runs off the timed path.
 """
 from __future__ import annotations
@@ -24,6 +25,8 @@ from ._lib import check, load
 ARCH = "gfx950"
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
 MAX_REQUEST = 4   # the deepest tdepth a caller can request of lope_iterate
+# the tuning table's boundary-rule classes (lope_tuning.rules)
+RULE_NAMES = ("periodic", "dirichlet")
 
 
 def _variant_table():
@@ -122,8 +125,10 @@ def autotune(a, b, stencil, bc, sweeps=24, chunks=(0, 16, 32, 64, 128), tdepths=
         if d not in choices or r["s_per_sweep"] < choices[d]["s_per_sweep"]:
             choices[d] = r
     if register:
+        from . import rule_class
+        rules = rule_class(bc, a.ndim)
         for req, r in choices.items():
-            lope_tune_set(a, stencil, r["id"], req, r["chunk"])
+            lope_tune_set(a, stencil, r["id"], req, r["chunk"], bc=bc)
         if cache_path:
             st = stencil.coeffs if hasattr(stencil, "coeffs") else stencil
             key = _key(a.ndim, int(getattr(stencil, "radius", 0)),
@@ -131,8 +136,8 @@ def autotune(a, b, stencil, bc, sweeps=24, chunks=(0, 16, 32, 64, 128), tdepths=
                        math.prod(a.shape))
             cache = load_cache_file(cache_path)
             for req, r in choices.items():
-                cache["%s|%d" % (key, req)] = {"variant": r["variant"], "tdepth": r["tdepth"], "chunk": r["chunk"],
-                                               "gpts": round(r["gpts"], 2)}
+                cache["%s|%d|%s" % (key, req, RULE_NAMES[rules])] = {
+                    "variant": r["variant"], "tdepth": r["tdepth"], "chunk": r["chunk"], "gpts": round(r["gpts"], 2)}
             with open(cache_path, "w") as f:
                 json.dump(cache, f, indent=1, sort_keys=True)
     return best, results
@@ -158,7 +163,11 @@ def register_cache(path=None) -> int:
         parts = key.split("|")
         if len(parts) == 6:
             parts.append("0")
-        arch, ndim, radius, dt, shape, bucket, req = parts
+        if len(parts) == 7:
+            parts.append(RULE_NAMES[0])
+        arch, ndim, radius, dt, shape, bucket, req, rules = parts
+        if rules not in RULE_NAMES:
+            continue
         req = int(req)
         if arch != ARCH or v["variant"] not in names:
             continue
@@ -197,7 +206,7 @@ def register_cache(path=None) -> int:
         s.ndim = ndim
         s.radius = radius
         s.coeffs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        t = _lib.lope_tuning(names[v["variant"]], req, int(v["chunk"]), 0)
+        t = _lib.lope_tuning(names[v["variant"]], req, int(v["chunk"]), RULE_NAMES.index(rules))
         if lib.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(t)) == 0:
             count += 1
     return count
@@ -213,6 +222,8 @@ def _workloads():
         ("heat3d512", lambda: synth.case_heat3d(512, np.float32, 10), (0, 16, 32, 64, 128)),
         ("heat3d256f64", lambda: synth.case_heat3d(256, np.float64, 10), (0, 16, 32, 64, 128)),
         ("box9", lambda: synth.case_box9(8192, 10), (0, 32, 64, 128, 256)),
+        ("heat3d512dir", lambda: synth.case_heat3d(512, np.float32, 10)._replace(
+            bc=synth.Boundary((synth.DIRICHLET,) * 3, 0.0)), (0, 16, 32, 64, 128)),
         ("star25", lambda: synth.case_star25(512, 10), (0, 32, 64, 128)),
         ("heat2d", lambda: synth.case_heat2d(256, 10), (0, 2, 4, 8, 16, 32, 64)),
     ]

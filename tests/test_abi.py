@@ -234,27 +234,43 @@ def test_variant_selection_and_tuning_table():
     arr[13] = 1.0
     arr[12] = arr[14] = arr[10] = arr[16] = arr[4] = arr[22] = 0.1     # 7-point star
     g = grid(n=(64, 64, 64))
-    v1 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 1)
+    v1 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 1)
     assert v1 > 0
     buf = ctypes.create_string_buffer(256)
     L.lope_variant_info(v1, buf, 256)
     assert b"star3d" in buf.value and b"tdepth=1" in buf.value
-    v2 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 2)
+    v2 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 2)
     L.lope_variant_info(v2, buf, 256)
     assert b"tdepth=2" in buf.value
-    v0 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0)
+    v0 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 0)
     t = _lib.lope_tuning(v2, 0, 32, 0)
     assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(t)) == 0
-    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0) == v2
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 0) == v2
     # variant 0 removes the choice: the request falls back to the default
     for req in (0, 3):
         clear = _lib.lope_tuning(0, req, 0, 0)
         assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(clear)) == 0
-    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0) == v0
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 0) == v0
     bad = _lib.lope_tuning(0, 5, 0, 0)
     assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(bad)) == _lib.LOPE_ERR_INVALID_ARG
+    # choices are kept per boundary-rule class: a Dirichlet-class choice does
+    # not answer all-periodic requests, and the other way round
+    dirichlet = bc(kind=_lib.LOPE_BC_DIRICHLET)
+    vd0 = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), ctypes.byref(dirichlet), 0)
+    td = _lib.lope_tuning(v2, 0, 32, 1)
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(td)) == 0
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), ctypes.byref(dirichlet), 0) == v2
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 0) == v0
+    mixed = bc()
+    mixed.kind[2] = _lib.LOPE_BC_DIRICHLET                                   # one Dirichlet axis: same class
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), ctypes.byref(mixed), 0) == v2
+    clear = _lib.lope_tuning(0, 0, 0, 1)
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(clear)) == 0
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), ctypes.byref(dirichlet), 0) == vd0
+    bad = _lib.lope_tuning(v2, 0, 0, 2)
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(bad)) == _lib.LOPE_ERR_INVALID_ARG
     box, _kb = stencil(ndim=3, r=1, fill=0.1)                            # 3D box: generic kernel
-    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(box), 1) == 0
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(box), None, 1) == 0
 
 
 def test_grid_views_match_descriptor():
@@ -408,7 +424,7 @@ def test_tune_cache_registration(tmp_path):
     for i in (4, 10, 12, 14, 16, 22):
         _keep[i] = 0.1
     g = grid(n=(64, 64, 64))          # 2^18 points: bucket 18
-    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 0) == names[t2]
-    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), 1) == names[t1]
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 0) == names[t2]
+    assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 1) == names[t1]
     bad = _lib.lope_tuning(names[t2], 1, 0, 0)       # depth 1 request answered by a depth-2 variant
     assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(bad)) == _lib.LOPE_ERR_INVALID_ARG

@@ -121,8 +121,8 @@ def test_residual_from_each_fused_3d_kernel(kinds):
     try:
         for vid, info in fused:
             td = int(info.split("tdepth=")[1].split()[0])
-            L.lope_tune_set(probe, st, vid, td)
-            L.lope_tune_set(probe, st, vid, 0)
+            L.lope_tune_set(probe, st, vid, td, bc=bc)
+            L.lope_tune_set(probe, st, vid, 0, bc=bc)
             a, b = grid_from(u0, 1), empty_grid(u0.shape, 1, np.float32)
             idx, steps, r = L.lope_iterate_until(a, b, st, bc, 12, 6, -1.0, tdepth=td)
             assert steps == 12, info
@@ -130,7 +130,7 @@ def test_residual_from_each_fused_3d_kernel(kinds):
             assert r == _max_diff(want, want_prev), info
     finally:
         for td in (0, 2, 3, 4):
-            L.lope_tune_set(probe, st, 0, td)
+            L.lope_tune_set(probe, st, 0, td, bc=bc)
 
 
 def test_special_cases():

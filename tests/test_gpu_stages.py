@@ -84,12 +84,12 @@ def test_two_steps_per_pass_each_wave_kernel(kinds):
     probe = grid_from(u, 1)
     try:
         for vid, info in waves:
-            L.lope_tune_set(probe, s1, vid, 4)
+            L.lope_tune_set(probe, s1, vid, 4, bc=bc)
             got = _run(u, s1, s2, 0.45, bc, n).numpy()
             assert rel_err(got, want) <= TOL[np.float32] * 2 * n, info
             np.testing.assert_array_equal(_run(u, s1, s2, 0.0, bc, n).numpy(), composed, err_msg=info)
     finally:
-        L.lope_tune_set(probe, s1, 0, 4)
+        L.lope_tune_set(probe, s1, 0, 4, bc=bc)
 
 
 def test_first_stencil_reach_sets_the_halo():
