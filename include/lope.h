@@ -25,6 +25,11 @@
  *   - Asynchronous: every compute call enqueues work on `stream` (a
  *     hipStream_t; NULL means the legacy default stream) and returns without
  *     synchronising; a kernel fault surfaces at the caller's next sync.
+ *   - Graph capture: the compute calls enqueue kernel launches only (no
+ *     memset or copy nodes, no host wait), so a stream being captured records
+ *     them into the caller's graph; the exceptions are lope_iterate_until,
+ *     which waits on the host and refuses a capturing stream, and the batch
+ *     plan calls, whose own rules are given with them.
  *   - Errors: every call returns LOPE_OK (0) or a negative lope_status.  All
  *     structural validation runs before any HIP call; on error nothing has
  *     been enqueued.  No exception crosses the ABI, nothing calls exit(), and
@@ -225,8 +230,9 @@ int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stenci
  * rule (periodic axes wrap; Dirichlet halo cells contribute zero).  If
  * gbar_dirichlet is not NULL it is a DEVICE pointer to one double that
  * receives (overwritten) dL/dg = sum_x ybar[x] * (sum of c_o over the taps of
- * x that read a Dirichlet halo cell).  The reflected stencil reaches the other
- * way: ybar's halo must cover the forward reach mirrored (left <-> right). */
+ * x that read a Dirichlet halo cell), summed in float64; workgroups add
+ * their partial sums atomically, so its last bits may differ from run to run.
+ * The reflected stencil reaches the other way: ybar's halo must cover the forward reach mirrored (left <-> right). */
 int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_stencil* st,
                        const lope_bc* bc, double* gbar_dirichlet, void* stream);
 
