@@ -1,6 +1,8 @@
 // Generic kernels: one-thread-per-point sweep for any stencil the tuned
 // families do not cover, the stored-halo fill, gradient folding and the
 // Dirichlet-value gradient reduction.
+#include <atomic>
+
 #include "lope_internal.h"
 
 namespace lope {
@@ -155,6 +157,27 @@ int grid_blocks(int64_t total) {
 }
 
 }  // namespace
+
+int device_cu_count() {
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int> cached[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    if (dev < kMaxDevices) {
+        const int c = cached[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        n = 256;
+    }
+    if (dev < kMaxDevices) cached[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
 
 hipError_t launch_generic(const SweepJob& j, hipStream_t s) {
     const int64_t total = (int64_t)j.src.nx * j.src.ny * j.src.nz;

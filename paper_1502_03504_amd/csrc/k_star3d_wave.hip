@@ -324,10 +324,14 @@ Coef7<T> coef7(const SweepJob& j) {
 template <typename T, int TD, int P, int NW, int PF, int WPE, int STG>
 hipError_t launch_wave3(const SweepJob& j, const Coef7<T>& cf, const Coef7<T>& cf2, T alpha, int chunk,
                         hipStream_t s) {
-    if (chunk <= 0) chunk = 64;
     const int out_cols = 64 - 2 * TD;
     const int strips = (j.src.nx + out_cols - 1) / out_cols;
     const int segs = (j.src.ny + P - 1) / P;
+    // automatic z-chunk: as long as the resident waves (WPE per SIMD, four
+    // SIMDs per compute unit) still cover every chunk in few rounds
+    if (chunk <= 0)
+        chunk = balanced_chunk((int64_t)strips * segs, j.src.nz, (int64_t)device_cu_count() * 4 * WPE, 2 * TD + 2,
+                                2 * TD);
     const int chunks = (j.src.nz + chunk - 1) / chunk;
     const int64_t nw64 = (int64_t)strips * segs * chunks;
     if (nw64 > (1ll << 30)) return hipErrorInvalidConfiguration;
@@ -376,11 +380,12 @@ hipError_t run_star3d_wave_stages(const StageJob& sj, int chunk, hipStream_t s) 
      64 - 2 * (TD), P, (NW) * 64, CH, &run_star3d_wave<T, TD, P, NW, PF, WPE>, 1,                           \
      &run_star3d_wave_stages<T, TD, P, NW, PF, WPE>}
 
-// WPE: waves per SIMD asked of the register allocator (1 = no request)
+// WPE: waves per SIMD asked of the register allocator (1 = no request);
+// default z-chunk 0: the automatic (round-balanced) chunk of the launcher
 const Variant kStar3dWave[] = {
-    WSTAR(float, LOPE_F32, 4, 8, 4, 1, 2, 32),
-    WSTAR(float, LOPE_F32, 4, 10, 4, 1, 2, 32),
-    WSTAR(float, LOPE_F32, 4, 6, 4, 1, 2, 32),
+    WSTAR(float, LOPE_F32, 4, 8, 4, 1, 2, 0),
+    WSTAR(float, LOPE_F32, 4, 10, 4, 1, 2, 0),
+    WSTAR(float, LOPE_F32, 4, 6, 4, 1, 2, 0),
 };
 
 }  // namespace

@@ -184,4 +184,33 @@ inline int padded_block_count(int nblocks) {
     return ((nblocks + kNumXcd - 1) / kNumXcd) * kNumXcd;
 }
 
+// Compute units of the current device (queried once per device; 256 on
+// MI355X if the query fails).
+int device_cu_count();
+
+// Marching kernels split each column of tiles into k z-chunks of
+// ceil(nz / k) planes; the launch then runs in ceil(ncols * k / slots)
+// rounds of resident waves, each round costing a chunk plus `warm` march
+// steps of start-up.  Returns the chunk (at least min_chunk, which bounds
+// the re-read planes per chunk) of the k that minimises
+// rounds * (chunk + warm), the smallest such chunk on ties.
+inline int balanced_chunk(int64_t ncols, int nz, int64_t slots, int warm, int min_chunk) {
+    if (nz <= 1 || ncols <= 0 || slots <= 0) return nz > 0 ? nz : 1;
+    int best_chunk = nz;
+    int64_t best_cost = -1;
+    const int kmax = nz < 512 ? nz : 512;
+    for (int k = 1; k <= kmax; ++k) {
+        const int chunk = (nz + k - 1) / k;
+        if (chunk < min_chunk) break;
+        const int kk = (nz + chunk - 1) / chunk;   // chunks actually made
+        const int64_t rounds = (ncols * kk + slots - 1) / slots;
+        const int64_t cost = rounds * (chunk + warm);
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && chunk < best_chunk)) {
+            best_cost = cost;
+            best_chunk = chunk;
+        }
+    }
+    return best_chunk;
+}
+
 }  // namespace lope

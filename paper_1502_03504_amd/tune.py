@@ -231,9 +231,15 @@ def _workloads():
 
 def tune_workloads(path, names=None, log=None):
     """Time every fitting (variant, chunk) on the benchmark workloads and write
-    the choices to the JSON table at `path` (replaced).  Needs a GPU."""
+    the choices to the JSON table at `path`: replaced when every workload is
+    tuned; with `names`, only the keys those workloads write change.  Needs a
+    GPU."""
     from . import Grid
+    kept = {}
     if os.path.exists(path):
+        if names:
+            with open(path) as f:
+                kept = json.load(f)
         os.remove(path)
     out = {}
     for name, make, chunks in _workloads():
@@ -250,6 +256,14 @@ def tune_workloads(path, names=None, log=None):
             log("best: %s" % best)
         del a, b, case
         torch.cuda.empty_cache()
+    if kept:
+        fresh = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                fresh = json.load(f)
+        kept.update(fresh)
+        with open(path, "w") as f:
+            json.dump(kept, f, indent=1, sort_keys=True)
     return out
 
 
