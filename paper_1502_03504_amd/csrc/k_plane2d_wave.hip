@@ -31,9 +31,14 @@ Coef9<T> coef9(const SweepJob& j) {
 template <typename T, int TD, bool BOX, int NW, int STG>
 hipError_t launch_wave(const SweepJob& j, const Coef9<T>& cf, const Coef9<T>& cf2, T alpha, int chunk,
                        hipStream_t s) {
-    if (chunk <= 0) chunk = 128;
     const int out_cols = 64 - 2 * TD;
     const int strips = (j.src.nx + out_cols - 1) / out_cols;
+    // automatic row chunk: as long as the resident waves still cover every
+    // chunk in few rounds
+    if (chunk <= 0) {
+        static const int bpc = blocks_per_cu(k_plane2d_wave<T, TD, BOX, NW, false, false, false, STG>, NW * 64);
+        chunk = balanced_chunk(strips, j.src.ny, (int64_t)device_cu_count() * bpc * NW, 2 * TD + 2, 2 * TD);
+    }
     const int chunks = (j.src.ny + chunk - 1) / chunk;
     const int64_t nw64 = (int64_t)strips * chunks;
     if (nw64 > (1ll << 30)) return hipErrorInvalidConfiguration;
@@ -87,23 +92,23 @@ hipError_t run_plane2d_wave_stages(const StageJob& sj, int chunk, hipStream_t s)
      (TD) == 2 ? &run_plane2d_wave_stages<T, TD, BOX, NW> : nullptr}
 
 const Variant kPlane2dWave[] = {
-    PWAVE(float, LOPE_F32, 1, true, 4, 128),
-    PWAVE(float, LOPE_F32, 2, true, 4, 128),
-    PWAVE(float, LOPE_F32, 3, true, 4, 128),
-    PWAVE(float, LOPE_F32, 4, true, 4, 128),
-    PWAVE(float, LOPE_F32, 5, true, 4, 128),
-    PWAVE(float, LOPE_F32, 6, true, 4, 128),
-    PWAVE(float, LOPE_F32, 8, true, 4, 128),
-    PWAVE(float, LOPE_F32, 1, false, 4, 128),
-    PWAVE(float, LOPE_F32, 2, false, 4, 128),
-    PWAVE(float, LOPE_F32, 3, false, 4, 128),
-    PWAVE(float, LOPE_F32, 4, false, 4, 128),
-    PWAVE(double, LOPE_F64, 1, false, 4, 32),
-    PWAVE(double, LOPE_F64, 2, false, 4, 32),
-    PWAVE(double, LOPE_F64, 4, false, 4, 32),
-    PWAVE(double, LOPE_F64, 6, false, 4, 32),
-    PWAVE(double, LOPE_F64, 8, false, 4, 32),
-    PWAVE(double, LOPE_F64, 2, true, 4, 32),
+    PWAVE(float, LOPE_F32, 1, true, 4, 0),
+    PWAVE(float, LOPE_F32, 2, true, 4, 0),
+    PWAVE(float, LOPE_F32, 3, true, 4, 0),
+    PWAVE(float, LOPE_F32, 4, true, 4, 0),
+    PWAVE(float, LOPE_F32, 5, true, 4, 0),
+    PWAVE(float, LOPE_F32, 6, true, 4, 0),
+    PWAVE(float, LOPE_F32, 8, true, 4, 0),
+    PWAVE(float, LOPE_F32, 1, false, 4, 0),
+    PWAVE(float, LOPE_F32, 2, false, 4, 0),
+    PWAVE(float, LOPE_F32, 3, false, 4, 0),
+    PWAVE(float, LOPE_F32, 4, false, 4, 0),
+    PWAVE(double, LOPE_F64, 1, false, 4, 0),
+    PWAVE(double, LOPE_F64, 2, false, 4, 0),
+    PWAVE(double, LOPE_F64, 4, false, 4, 0),
+    PWAVE(double, LOPE_F64, 6, false, 4, 0),
+    PWAVE(double, LOPE_F64, 8, false, 4, 0),
+    PWAVE(double, LOPE_F64, 2, true, 4, 0),
 };
 
 }  // namespace

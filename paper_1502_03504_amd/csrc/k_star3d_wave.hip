@@ -327,11 +327,14 @@ hipError_t launch_wave3(const SweepJob& j, const Coef7<T>& cf, const Coef7<T>& c
     const int out_cols = 64 - 2 * TD;
     const int strips = (j.src.nx + out_cols - 1) / out_cols;
     const int segs = (j.src.ny + P - 1) / P;
-    // automatic z-chunk: as long as the resident waves (WPE per SIMD, four
-    // SIMDs per compute unit) still cover every chunk in few rounds
-    if (chunk <= 0)
-        chunk = balanced_chunk((int64_t)strips * segs, j.src.nz, (int64_t)device_cu_count() * 4 * WPE, 2 * TD + 2,
-                                2 * TD);
+    // automatic z-chunk: as long as the resident waves (the workgroups a
+    // compute unit holds at the compiled register use, on every unit) still
+    // cover every chunk in few rounds
+    if (chunk <= 0) {
+        static const int bpc = blocks_per_cu(k_star3d_wave<T, TD, P, NW, false, false, false, STG, PF, WPE>, NW * 64);
+        chunk = balanced_chunk((int64_t)strips * segs, j.src.nz, (int64_t)device_cu_count() * bpc * NW, 2 * TD + 2,
+                               2 * TD);
+    }
     const int chunks = (j.src.nz + chunk - 1) / chunk;
     const int64_t nw64 = (int64_t)strips * segs * chunks;
     if (nw64 > (1ll << 30)) return hipErrorInvalidConfiguration;

@@ -188,6 +188,19 @@ inline int padded_block_count(int nblocks) {
 // MI355X if the query fails).
 int device_cu_count();
 
+// Workgroups of `kernel` (block_threads threads, no dynamic LDS) that one
+// compute unit holds at once, from the compiled register and LDS use (1 if
+// the query fails).
+template <typename K>
+inline int blocks_per_cu(K kernel, int block_threads) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block_threads, 0) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        n = 1;
+    }
+    return n;
+}
+
 // Marching kernels split each column of tiles into k z-chunks of
 // ceil(nz / k) planes; the launch then runs in ceil(ncols * k / slots)
 // rounds of resident waves, each round costing a chunk plus `warm` march
