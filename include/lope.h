@@ -150,7 +150,11 @@ typedef struct lope_tuning {
     int32_t variant;              /* kernel variant id from lope_variant_info, 0 = automatic,
                                      LOPE_VARIANT_GENERIC = the one-thread-per-point kernel */
     int32_t tdepth;               /* sweeps fused per pass, 1..4; 0 = automatic */
-    int32_t chunk;                /* extent of the marched axis per workgroup; 0 = automatic */
+    int32_t chunk;                /* extent of the marched axis per workgroup or wave; 0 =
+                                     automatic: the wave kernels cut each column of tiles into
+                                     chunks as long as the device's resident waves (at the
+                                     kernel's compiled occupancy) still cover in few rounds,
+                                     the others use a fixed default */
     int32_t rules;                /* lope_tune_set: the boundary-rule class the choice is for,
                                      0 = periodic on every axis, 1 = some axis Dirichlet;
                                      ignored by lope_iterate_tuned */
