@@ -211,18 +211,22 @@ inline int balanced_chunk(int64_t ncols, int nz, int64_t slots, int warm, int mi
     if (nz <= 1 || ncols <= 0 || slots <= 0) return nz > 0 ? nz : 1;
     int best_chunk = nz;
     int64_t best_cost = -1;
-    const int kmax = nz < 512 ? nz : 512;
-    for (int k = 1; k <= kmax; ++k) {
-        const int chunk = (nz + k - 1) / k;
-        if (chunk < min_chunk) break;
-        const int kk = (nz + chunk - 1) / chunk;   // chunks actually made
+    auto consider = [&](int64_t k) {
+        if (k < 1 || k > nz) return;
+        const int chunk = (int)((nz + k - 1) / k);
+        if (chunk < min_chunk && chunk < nz) return;
+        const int64_t kk = (nz + chunk - 1) / chunk;   // chunks actually made
         const int64_t rounds = (ncols * kk + slots - 1) / slots;
         const int64_t cost = rounds * (chunk + warm);
         if (best_cost < 0 || cost < best_cost || (cost == best_cost && chunk < best_chunk)) {
             best_cost = cost;
             best_chunk = chunk;
         }
-    }
+    };
+    // every small k, and the k that fill one to eight whole rounds (tall
+    // columns on few tiles need more than 512 chunks)
+    for (int k = 1; k <= 512; ++k) consider(k);
+    for (int64_t m = 1; m <= 8; ++m) consider(m * slots / ncols);
     return best_chunk;
 }
 

@@ -126,6 +126,32 @@ def test_wave_brick_kernels_edge_shapes(shape):
                 np.testing.assert_array_equal((a, b)[idx].numpy(), ref, err_msg="%s chunk %d %s" % (info, chunk, kinds))
 
 
+@pytest.mark.parametrize("shape,dtype,kind", [((120000, 40), np.float32, "box"), ((30000, 100), np.float64, "star"),
+                                              ((80000, 9, 2), np.float32, "star")])
+def test_wave_kernels_tall_columns(shape, dtype, kind):
+    """Columns of tiles far longer than wide (one or two strips of 2D rows, a
+    3D z axis of 80000 planes): the automatic chunk then cuts each column
+    into thousands of chunks.  Every wave variant at every depth, automatic
+    chunk, against one sweep per pass (bitwise) and the oracle."""
+    rng = np.random.default_rng([synth.CFG_TEST, 130 + len(shape)])
+    ndim = len(shape)
+    st = synth.contractive(synth.random_stencil(rng, ndim, 1, kind))
+    prefix = "star3dw_" if ndim == 3 else "plane2dw_"
+    u = rng.uniform(-1, 1, size=shape).astype(dtype)
+    n = 8
+    kinds = (D, P, D)[:ndim] if ndim == 3 else (P, D)
+    want = oracle.iterate(u, st.coeffs, kinds, 0.5, n)
+    x, y = grid_from(u, 1), empty_grid(u.shape, 1, dtype)
+    ref = (x, y)[L.lope_iterate(x, y, st, (kinds, 0.5), n, tdepth=1)].numpy()
+    assert rel_err(ref, want) <= tol(dtype) * n
+    waves = [(vid, info) for vid, info in variants_for(ndim, 1, dtype, shape=kind) if info.startswith(prefix)]
+    assert waves
+    for vid, info in waves:
+        a, b = grid_from(u, 1), empty_grid(u.shape, 1, dtype)
+        idx = L.lope_iterate_tuned(a, b, st, (kinds, 0.5), n, variant=vid, chunk=0)
+        np.testing.assert_array_equal((a, b)[idx].numpy(), ref, err_msg=info)
+
+
 @pytest.mark.parametrize("n_steps", [0, 1, 2, 5, 8])
 def test_iterate_result_index_and_auto_depth(n_steps):
     u = _field((21, 40, 66), np.float32, 4)
