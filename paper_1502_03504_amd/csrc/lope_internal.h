@@ -211,10 +211,8 @@ inline int balanced_chunk(int64_t ncols, int nz, int64_t slots, int warm, int mi
     if (nz <= 1 || ncols <= 0 || slots <= 0) return nz > 0 ? nz : 1;
     int best_chunk = nz;
     int64_t best_cost = -1;
-    auto consider = [&](int64_t k) {
-        if (k < 1 || k > nz) return;
-        const int chunk = (int)((nz + k - 1) / k);
-        if (chunk < min_chunk && chunk < nz) return;
+    auto consider_chunk = [&](int chunk) {
+        if (chunk < 1 || chunk > nz || (chunk < min_chunk && chunk < nz)) return;
         const int64_t kk = (nz + chunk - 1) / chunk;   // chunks actually made
         const int64_t rounds = (ncols * kk + slots - 1) / slots;
         const int64_t cost = rounds * (chunk + warm);
@@ -223,10 +221,16 @@ inline int balanced_chunk(int64_t ncols, int nz, int64_t slots, int warm, int mi
             best_chunk = chunk;
         }
     };
-    // every small k, and the k that fill one to eight whole rounds (tall
-    // columns on few tiles need more than 512 chunks)
+    auto consider = [&](int64_t k) {
+        if (k >= 1 && k <= nz) consider_chunk((int)((nz + k - 1) / k));
+    };
+    // the even cuts into k chunks for every small k and for the k that fill
+    // one to eight whole rounds (tall columns on few tiles need more than
+    // 512 chunks), and the shortest admissible chunk (the best one wherever
+    // the even cut would fall below the minimum)
     for (int k = 1; k <= 512; ++k) consider(k);
     for (int64_t m = 1; m <= 8; ++m) consider(m * slots / ncols);
+    consider_chunk(min_chunk);
     return best_chunk;
 }
 
