@@ -229,14 +229,20 @@ int lope_iterate_until(const lope_grid* a, const lope_grid* b, const lope_stenci
                        int32_t tdepth, double* residual_scratch, void* stream,
                        int64_t* steps_done, double* residual, int32_t* result_index);
 
+/* Doubles of the array lope_apply_adjoint's gbar_dirichlet points to. */
+#define LOPE_GBAR_DOUBLES 1024
+
 /* Adjoint sweep: xbar interior = S^T(ybar), the transpose of the linear part
  * of lope_apply: the reflected stencil c_{-o} applied with the transposed
  * rule (periodic axes wrap; Dirichlet halo cells contribute zero).  If
- * gbar_dirichlet is not NULL it is a DEVICE pointer to one double that
- * receives (overwritten) dL/dg = sum_x ybar[x] * (sum of c_o over the taps of
- * x that read a Dirichlet halo cell), summed in float64; workgroups add
- * their partial sums atomically, so its last bits may differ from run to run.
- * The reflected stencil reaches the other way: ybar's halo must cover the forward reach mirrored (left <-> right). */
+ * gbar_dirichlet is not NULL it is a DEVICE pointer to LOPE_GBAR_DOUBLES
+ * 8-byte aligned doubles (caller-owned workspace, checked to lie in one
+ * device allocation): the call overwrites them, and once it has run element
+ * 0 holds dL/dg = sum_x ybar[x] * (sum of c_o over the taps of x that read a
+ * Dirichlet halo cell), summed in float64 in a fixed order (per-workgroup
+ * sums in elements 0.., then their sum), so equal inputs give equal bits on
+ * every run.  The reflected stencil reaches the other way: ybar's halo must
+ * cover the forward reach mirrored (left <-> right). */
 int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_stencil* st,
                        const lope_bc* bc, double* gbar_dirichlet, void* stream);
 
@@ -343,10 +349,26 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream);
  * grid per sweep (the baseline the batched launch is compared with). */
 int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream);
 
-/* Sweeps fused per launch (1..8, default 2): passes of tdepth sweeps, the
- * remainder of n_steps in one shorter pass.  Builds the plan's tile table for
- * the depth if needed (synchronous upload). */
+/* Tiling of the batched passes: tdepth sweeps fused per launch (1..8; the
+ * remainder of n_steps in one shorter pass) and strips of `rows` rows
+ * (1..65536; 0 keeps the current rows).  A new plan starts with the tiling
+ * registered by lope_batch_tune_set for its dtype and the size bucket of its
+ * total interior points (else the nearest registered bucket of the dtype,
+ * else 4 sweeps and 128 rows).  Builds the plan's tile tables for the tiling
+ * if needed (synchronous upload); on error the plan keeps its tiling. */
+int lope_batch_plan_set_tiles(lope_batch_plan* plan, int32_t tdepth, int32_t rows);
+
+/* lope_batch_plan_set_tiles(plan, tdepth, 0). */
 int lope_batch_plan_set_depth(lope_batch_plan* plan, int32_t tdepth);
+
+/* The plan's current tiling.  No pointer may be NULL. */
+int lope_batch_plan_get_tiles(const lope_batch_plan* plan, int32_t* tdepth, int32_t* rows);
+
+/* Register the tiling new batch plans of dtype `dtype` take when their total
+ * interior points fall in the bucket floor(log2(points)) (the autotuner's
+ * choice): tdepth 1..8 and rows 1..65536; tdepth 0 removes the entry of that
+ * bucket.  Only argument checks (no device access). */
+int lope_batch_tune_set(int32_t dtype, int64_t points, int32_t tdepth, int32_t rows);
 
 /* *out = 0 if lope_batch_apply leaves every grid's state in its src, 1 if in
  * its dst (the parity of the number of passes).  out must not be NULL. */
@@ -380,10 +402,12 @@ int lope_select_variant(const lope_grid* g, const lope_stencil* st, const lope_b
  * 0 = lope_iterate with tdepth 0 (automatic), k = lope_iterate with tdepth k
  * (then the variant's own depth must be k).  The key is (ndim, radius,
  * dtype, star/box shape, size bucket = floor(log2(interior points)),
- * requested depth, rule class tune->rules).  tune->variant = 0 removes the
- * choice registered for that
- * request (tdepth 0..4), so the request falls back to the default variant.
- * Only structural checks are made (no device access). */
+ * requested depth, rule class tune->rules).  A request whose own bucket has
+ * no fitting choice takes the variant and depth registered for the nearest
+ * bucket of its class (the larger one on a tie), with the automatic chunk;
+ * with no choice in the class at all it takes the default variant.
+ * tune->variant = 0 removes the choice registered for that request (tdepth
+ * 0..4) and bucket.  Only structural checks are made (no device access). */
 int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning* tune);
 
 #ifdef __cplusplus

@@ -22,10 +22,11 @@ from ._lib import LopeError, check, load
 
 __all__ = [
     "Grid", "LopeError", "lope_get_device", "lope_halo_fill", "lope_apply", "lope_iterate",
-    "lope_iterate_tuned", "lope_iterate_until", "lope_apply_stages", "lope_iterate_stages", "lope_apply_adjoint", "lope_apply_var", "lope_apply_var_adjoint",
+    "lope_iterate_tuned", "lope_iterate_until", "lope_apply_stages", "lope_iterate_stages", "lope_apply_adjoint",
+    "gbar_buffer", "LOPE_GBAR_DOUBLES", "lope_apply_var", "lope_apply_var_adjoint",
     "lope_accumulate", "lope_variant_count", "lope_variant_info", "lope_select_variant",
     "lope_tune_set", "variants", "BatchPlan", "lope_batch_plan_create", "lope_batch_apply",
-    "lope_batch_apply_per_grid", "lope_batch_plan_destroy", "DIRICHLET", "PERIODIC",
+    "lope_batch_apply_per_grid", "lope_batch_plan_destroy", "lope_batch_tune_set", "DIRICHLET", "PERIODIC",
 ]
 
 DIRICHLET = "dirichlet"
@@ -320,15 +321,26 @@ def lope_iterate_stages(a: Grid, b: Grid, first, second, alpha: float, bc, n_ste
     return idx.value
 
 
+LOPE_GBAR_DOUBLES = 1024   # doubles of the array lope_apply_adjoint's gbar points to
+
+
+def gbar_buffer(device="cuda", fill=0.0) -> torch.Tensor:
+    """A float64 device array for lope_apply_adjoint's gbar (element 0 gets
+    dL/dg; the rest is the call's workspace)."""
+    return torch.full((LOPE_GBAR_DOUBLES,), float(fill), dtype=torch.float64, device=device)
+
+
 def lope_apply_adjoint(ybar: Grid, xbar: Grid, stencil, bc, gbar: torch.Tensor = None, stream=None) -> None:
-    """xbar = S^T ybar; if ``gbar`` (a float64 device tensor of one element) is
-    given it receives dL/dg."""
+    """xbar = S^T ybar; if ``gbar`` (a float64 device tensor of at least
+    LOPE_GBAR_DOUBLES elements, see gbar_buffer) is given, gbar[0] receives
+    dL/dg and the other elements are overwritten."""
     s = _Stencil(stencil)
     a, b = ybar.descriptor(), xbar.descriptor()
     gp = None
     if gbar is not None:
-        if gbar.dtype != torch.float64 or gbar.numel() < 1 or not gbar.is_cuda:
-            raise TypeError("gbar must be a float64 device tensor")
+        if gbar.dtype != torch.float64 or gbar.numel() < LOPE_GBAR_DOUBLES or not gbar.is_cuda \
+                or not gbar.is_contiguous():
+            raise TypeError("gbar must be a contiguous float64 device tensor of %d elements" % LOPE_GBAR_DOUBLES)
         gp = ctypes.c_void_p(gbar.data_ptr())
     check(load().lope_apply_adjoint(_ref(a), _ref(b), _ref(s.c), _ref(_bc(bc, ybar.ndim)), gp, _stream(stream)))
 
@@ -408,4 +420,5 @@ def lope_tune_set(grid: Grid, stencil, variant: int, tdepth: int = 0, chunk: int
 
 from .batch import (  # noqa: E402,F401
     BatchPlan, lope_batch_plan_create, lope_batch_apply, lope_batch_apply_per_grid, lope_batch_plan_destroy,
+    lope_batch_tune_set,
 )

@@ -117,6 +117,9 @@ SIGNATURES = {
     "lope_batch_apply": (ctypes.c_int, [c_void_p, c_void_p]),
     "lope_batch_apply_per_grid": (ctypes.c_int, [c_void_p, c_void_p]),
     "lope_batch_plan_set_depth": (ctypes.c_int, [c_void_p, ctypes.c_int32]),
+    "lope_batch_plan_set_tiles": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "lope_batch_plan_get_tiles": (ctypes.c_int, [c_void_p, P(ctypes.c_int32), P(ctypes.c_int32)]),
+    "lope_batch_tune_set": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
     "lope_batch_result_index": (ctypes.c_int, [c_void_p, P(ctypes.c_int32)]),
     "lope_batch_plan_destroy": (ctypes.c_int, [c_void_p]),
     "lope_status_string": (ctypes.c_char_p, [ctypes.c_int]),

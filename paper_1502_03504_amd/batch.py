@@ -44,6 +44,16 @@ class BatchPlan:
         """Sweeps fused per launch (1..8)."""
         check(load().lope_batch_plan_set_depth(self.handle, int(tdepth)))
 
+    def set_tiles(self, tdepth: int, rows: int = 0) -> None:
+        """Sweeps fused per launch (1..8) and rows per strip (0 keeps them)."""
+        check(load().lope_batch_plan_set_tiles(self.handle, int(tdepth), int(rows)))
+
+    def tiles(self):
+        """(sweeps per launch, rows per strip) the plan runs with."""
+        d, r = ctypes.c_int32(-1), ctypes.c_int32(-1)
+        check(load().lope_batch_plan_get_tiles(self.handle, ctypes.byref(d), ctypes.byref(r)))
+        return d.value, r.value
+
     def result_index(self) -> int:
         v = ctypes.c_int32(-1)
         check(load().lope_batch_result_index(self.handle, ctypes.byref(v)))
@@ -83,3 +93,11 @@ def lope_batch_apply_per_grid(plan: BatchPlan, stream=None) -> None:
 
 def lope_batch_plan_destroy(plan: BatchPlan) -> None:
     plan.close()
+
+
+def lope_batch_tune_set(dtype, points: int, tdepth: int, rows: int) -> None:
+    """Register the tiling of batches of this dtype (torch dtype) and size
+    bucket (tdepth 0 removes it)."""
+    import torch
+    code = _lib.LOPE_F64 if dtype == torch.float64 else _lib.LOPE_F32
+    check(load().lope_batch_tune_set(code, int(points), int(tdepth), int(rows)))

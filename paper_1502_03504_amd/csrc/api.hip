@@ -388,6 +388,12 @@ int default_variant(const SweepJob& j, int tdepth) {
     return first;
 }
 
+// A chunk longer than every extent marches the whole axis; clamping keeps the
+// launchers' chunk-count arithmetic far from int overflow.
+int clamp_chunk(const SweepJob& j, int chunk) {
+    return std::min(chunk, std::max(j.src.nx, std::max(j.src.ny, j.src.nz)));
+}
+
 // One pass of `depth` sweeps from job.src to job.dst with variant id (0 = generic, depth 1).
 int run_pass(const SweepJob& j, int variant, int chunk, hipStream_t s) {
     hipError_t e;
@@ -395,7 +401,7 @@ int run_pass(const SweepJob& j, int variant, int chunk, hipStream_t s) {
         e = launch_generic(j, s);
     } else {
         const Variant& v = registry().v[variant - 1];
-        e = v.fn(j, chunk > 0 ? chunk : v.default_chunk, s);
+        e = v.fn(j, chunk > 0 ? clamp_chunk(j, chunk) : v.default_chunk, s);
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return LOPE_OK;
@@ -406,6 +412,42 @@ struct Plan {
     int tdepth;
     int chunk;
 };
+
+// The registered choice for a request of `req` sweeps per pass (0 = automatic)
+// on a job like j: the entry of j's own size bucket if its variant fits j,
+// else the fitting entry of the same class (ndim, radius, dtype, shape, request,
+// rule class) whose bucket is nearest (the larger on a tie); *exact says
+// which.  Caller holds g_tune_mu.
+const TuneChoice* tune_lookup(const SweepJob& j, int req, bool* exact) {
+    const int64_t pts = (int64_t)j.src.nx * j.src.ny * j.src.nz;
+    const TuneKey key = tune_key(j.ndim, j.radius, j.dtype, j.star, pts, req, rule_class(j));
+    auto fits = [&](const TuneChoice& c) {
+        return c.variant > 0 && variant_fits(registry().v[c.variant - 1], j, c.tdepth);
+    };
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && fits(it->second)) {
+        *exact = true;
+        return &it->second;
+    }
+    *exact = false;
+    const int bucket = std::get<4>(key);
+    const TuneChoice* best = nullptr;
+    int best_dist = 0, best_bucket = 0;
+    for (const auto& kv : g_tune) {
+        const TuneKey& k = kv.first;
+        if (std::get<0>(k) != std::get<0>(key) || std::get<1>(k) != std::get<1>(key) ||
+            std::get<2>(k) != std::get<2>(key) || std::get<3>(k) != std::get<3>(key) ||
+            std::get<5>(k) != std::get<5>(key) || std::get<6>(k) != std::get<6>(key) || !fits(kv.second))
+            continue;
+        const int b = std::get<4>(k), dist = b > bucket ? b - bucket : bucket - b;
+        if (!best || dist < best_dist || (dist == best_dist && b > best_bucket)) {
+            best = &kv.second;
+            best_dist = dist;
+            best_bucket = b;
+        }
+    }
+    return best;
+}
 
 Plan choose(const SweepJob& j, int tdepth_req, int variant_req, int chunk_req) {
     Plan p{0, 1, chunk_req};
@@ -419,13 +461,13 @@ Plan choose(const SweepJob& j, int tdepth_req, int variant_req, int chunk_req) {
     int td = tdepth_req;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        const int64_t pts = (int64_t)j.src.nx * j.src.ny * j.src.nz;
-        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts, td > 0 ? td : 0, rule_class(j)));
-        if (it != g_tune.end() && it->second.variant > 0 &&
-            variant_fits(registry().v[it->second.variant - 1], j, it->second.tdepth)) {
-            p.variant = it->second.variant;
-            p.tdepth = it->second.tdepth;
-            if (p.chunk <= 0) p.chunk = it->second.chunk;
+        bool exact = false;
+        if (const TuneChoice* c = tune_lookup(j, td > 0 ? td : 0, &exact)) {
+            p.variant = c->variant;
+            p.tdepth = c->tdepth;
+            // a chunk length was tuned for its own size; other sizes take
+            // the launcher's automatic chunk
+            if (p.chunk <= 0) p.chunk = exact ? c->chunk : 0;
             return p;
         }
     }
@@ -450,14 +492,11 @@ int residual_variant(const SweepJob& j, int depth, int* chunk) {
     *chunk = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        const int64_t pts = (int64_t)j.src.nx * j.src.ny * j.src.nz;
-        auto it = g_tune.find(tune_key(j.ndim, j.radius, j.dtype, j.star, pts, depth, rule_class(j)));
-        if (it != g_tune.end() && it->second.variant > 0 && it->second.tdepth == depth) {
-            const Variant& v = registry().v[it->second.variant - 1];
-            if (v.res && variant_fits(v, j, depth)) {
-                *chunk = it->second.chunk;
-                return it->second.variant;
-            }
+        bool exact = false;
+        const TuneChoice* c = tune_lookup(j, depth, &exact);
+        if (c && c->tdepth == depth && registry().v[c->variant - 1].res) {
+            *chunk = exact ? c->chunk : 0;
+            return c->variant;
         }
     }
     auto& R = registry().v;
@@ -514,8 +553,41 @@ int iterate_impl(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
 
 
 // ---- batch plans ----
-constexpr int kBatchRows = 128;       // rows per batch strip
-constexpr int kBatchDefaultDepth = 2; // sweeps per pass unless set
+constexpr int kBatchRows = 128;       // rows per batch strip unless tuned or set
+constexpr int kBatchDefaultDepth = 4; // sweeps per pass unless tuned or set
+constexpr int kBatchMaxRows = 1 << 16;
+
+// Batch tiling table: (dtype, floor(log2 interior points of the whole batch))
+// -> (sweeps per pass, rows per strip), registered by lope_batch_tune_set.
+std::mutex g_batch_tune_mu;
+std::map<std::pair<int, int>, std::pair<int, int>> g_batch_tune;
+
+int log2_bucket(int64_t points) {
+    int bucket = 0;
+    while (bucket < 62 && ((int64_t)1 << (bucket + 1)) <= points) ++bucket;
+    return bucket;
+}
+
+// The registered tiling for a batch of `points` interior points: its own
+// bucket, else the nearest registered bucket of the dtype (the larger on a
+// tie), else the defaults.
+void batch_tiling(int dtype, int64_t points, int* tdepth, int* rows) {
+    *tdepth = kBatchDefaultDepth;
+    *rows = kBatchRows;
+    const int bucket = log2_bucket(points);
+    std::lock_guard<std::mutex> lk(g_batch_tune_mu);
+    int best_dist = -1, best_bucket = 0;
+    for (const auto& kv : g_batch_tune) {
+        if (kv.first.first != dtype) continue;
+        const int b = kv.first.second, dist = b > bucket ? b - bucket : bucket - b;
+        if (best_dist < 0 || dist < best_dist || (dist == best_dist && b > best_bucket)) {
+            best_dist = dist;
+            best_bucket = b;
+            *tdepth = kv.second.first;
+            *rows = kv.second.second;
+        }
+    }
+}
 
 struct PlanGrid {
     lope_grid src, dst;
@@ -531,6 +603,7 @@ struct lope_batch_plan {
     int64_t n_steps = 0;
     int device = 0;
     int tdepth = kBatchDefaultDepth;
+    int rows = kBatchRows;            // rows per strip of the tile tables
     std::vector<PlanGrid> grids;
     std::vector<int64_t> order;       // grids in tile-table order (largest first, dealt to XCD ranges)
     std::vector<SweepJob> jobs;       // per-grid launches (the comparison path)
@@ -538,8 +611,9 @@ struct lope_batch_plan {
     BatchGrid* d_grids = nullptr;
     BatchItem* d_items[kBatchMaxDepth + 1] = {};   // tile tables per depth
     int nitems[kBatchMaxDepth + 1] = {};
-    hipGraphExec_t graph = nullptr;   // every pass of lope_batch_apply, recorded for graph_depth
-    int graph_depth = 0;
+    int items_rows[kBatchMaxDepth + 1] = {};   // rows per strip each table was built with
+    hipGraphExec_t graph = nullptr;   // every pass of lope_batch_apply, recorded for (graph_depth, graph_rows)
+    int graph_depth = 0, graph_rows = 0;
 };
 
 namespace {
@@ -554,27 +628,33 @@ void plan_free(lope_batch_plan* p) {
 }
 
 // Work table for passes of `depth` sweeps: per grid (in plan order), strips
-// of batch_strip_width(depth) output columns by chunks of kBatchRows rows,
-// one entry per wave.  Built and uploaded once per depth.
+// of batch_strip_width(depth) output columns by chunks of p->rows rows, one
+// entry per wave.  Built and uploaded once per (depth, rows).
 int plan_items(lope_batch_plan* p, int depth) {
-    if (p->d_items[depth]) return LOPE_OK;
+    if (p->d_items[depth] && p->items_rows[depth] == p->rows) return LOPE_OK;
+    if (p->d_items[depth]) {
+        (void)hipFree(p->d_items[depth]);
+        p->d_items[depth] = nullptr;
+    }
     std::vector<BatchItem> items;
-    const int64_t bw = batch_strip_width(depth);
+    const int64_t bw = batch_strip_width(depth), rows = p->rows;
     for (int64_t gi : p->order) {
         const lope_grid& g = p->grids[(size_t)gi].src;
         const int64_t nx = g.n[0], ny = g.n[1];
         if (nx == 0 || ny == 0) continue;
-        for (int64_t y0 = 0; y0 < ny; y0 += kBatchRows)
+        for (int64_t y0 = 0; y0 < ny; y0 += rows)
             for (int64_t x0 = 0; x0 < nx; x0 += bw) {
                 BatchItem it{};
                 it.grid = (int32_t)gi;
                 it.x0 = (int32_t)x0;
                 it.y0 = (int32_t)y0;
-                it.y1 = (int32_t)std::min(ny, y0 + kBatchRows);
+                it.y1 = (int32_t)std::min(ny, y0 + rows);
                 items.push_back(it);
             }
     }
+    if (items.size() > (size_t)(1 << 30)) return fail(LOPE_ERR_UNSUPPORTED, "batch tile table too long");
     p->nitems[depth] = (int)items.size();
+    p->items_rows[depth] = p->rows;
     if (items.empty()) return LOPE_OK;
     hipError_t e = hipMalloc(&p->d_items[depth], items.size() * sizeof(BatchItem));
     if (e == hipSuccess)
@@ -812,10 +892,11 @@ int stages_impl(const lope_grid* a, const lope_grid* b, const lope_stages* sg, c
         sj.s1.dst = (passes & 1) ? ga : gb;
         hipError_t e;
         if (v2 && n_steps - done >= 2) {
-            e = R[v2 - 1].sfn(sj, chunk2 > 0 ? chunk2 : R[v2 - 1].default_chunk, s);
+            e = R[v2 - 1].sfn(sj, chunk2 > 0 ? clamp_chunk(sj.s1, chunk2) : R[v2 - 1].default_chunk, s);
             done += 2;
         } else {
-            e = v1 ? R[v1 - 1].sfn(sj, chunk1 > 0 ? chunk1 : R[v1 - 1].default_chunk, s) : launch_stages_generic(sj, s);
+            e = v1 ? R[v1 - 1].sfn(sj, chunk1 > 0 ? clamp_chunk(sj.s1, chunk1) : R[v1 - 1].default_chunk, s)
+                   : launch_stages_generic(sj, s);
             done += 1;
         }
         if (e != hipSuccess) return hip_fail(e, "two-stage launch");
@@ -856,21 +937,25 @@ int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_
     if ((rc = check_alias(ybar, xbar, "ybar", "xbar"))) return rc;
     if ((rc = device_ready())) return rc;
     if ((rc = check_memory(ybar, "ybar")) || (rc = check_memory(xbar, "xbar"))) return rc;
-    if (gbar_dirichlet && (rc = check_device_pointer(gbar_dirichlet, sizeof(double), "gbar_dirichlet"))) return rc;
+    if (gbar_dirichlet && ((uintptr_t)gbar_dirichlet & 7))
+        return fail(LOPE_ERR_INVALID_ARG, "gbar_dirichlet must be 8-byte aligned");
+    if (gbar_dirichlet &&
+        (rc = check_device_pointer(gbar_dirichlet, LOPE_GBAR_DOUBLES * sizeof(double), "gbar_dirichlet")))
+        return rc;
     const hipStream_t s = (hipStream_t)stream;
     static thread_local SweepJob job;
     if (is_empty(ybar)) {
         if (gbar_dirichlet) {
             build_job(job, ybar, xbar, st, bc, false);
             job.src.nx = 0;
-            const hipError_t e = launch_gbar(job, gbar_dirichlet, s);
+            const hipError_t e = launch_gbar(job, gbar_dirichlet, gbar_dirichlet, s);
             if (e != hipSuccess) return hip_fail(e, "gbar launch");
         }
         return LOPE_OK;
     }
     if (gbar_dirichlet) {
         build_job(job, ybar, xbar, st, bc, false);
-        const hipError_t e = launch_gbar(job, gbar_dirichlet, s);
+        const hipError_t e = launch_gbar(job, gbar_dirichlet, gbar_dirichlet, s);
         if (e != hipSuccess) return hip_fail(e, "gbar launch");
     }
     build_job(job, ybar, xbar, st, bc, true);
@@ -1021,6 +1106,11 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
     lope_batch_plan* p = new lope_batch_plan();
     p->dtype = dtype;
     p->n_steps = n_steps;
+    {
+        int64_t points = 0;
+        for (int64_t i = 0; i < n_items; ++i) points += items[i].src.n[0] * items[i].src.n[1];
+        batch_tiling(dtype, points, &p->tdepth, &p->rows);
+    }
     (void)hipGetDevice(&p->device);
     // copy items (the stencil table is copied; grids are borrowed)
     p->grids.resize((size_t)n_items);
@@ -1091,15 +1181,47 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
     return LOPE_OK;
 }
 
-int lope_batch_plan_set_depth(lope_batch_plan* plan, int32_t tdepth) {
+int lope_batch_plan_set_tiles(lope_batch_plan* plan, int32_t tdepth, int32_t rows) {
     if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
     if (tdepth < 1 || tdepth > kBatchMaxDepth)
         return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 1..%d", tdepth, kBatchMaxDepth);
+    if (rows < 0 || rows > kBatchMaxRows) return fail(LOPE_ERR_INVALID_ARG, "rows %d not in 0..%d", rows, kBatchMaxRows);
     int rc;
     if ((rc = device_ready())) return rc;
+    const int old_depth = plan->tdepth, old_rows = plan->rows;
     plan->tdepth = tdepth;
-    if ((rc = plan_items(plan, tdepth))) return rc;
-    if (plan->n_steps % tdepth && (rc = plan_items(plan, (int)(plan->n_steps % tdepth)))) return rc;
+    if (rows > 0) plan->rows = rows;
+    if ((rc = plan_items(plan, tdepth)) ||
+        (plan->n_steps % tdepth && (rc = plan_items(plan, (int)(plan->n_steps % tdepth))))) {
+        plan->tdepth = old_depth;
+        plan->rows = old_rows;
+        return rc;
+    }
+    return LOPE_OK;
+}
+
+int lope_batch_plan_set_depth(lope_batch_plan* plan, int32_t tdepth) { return lope_batch_plan_set_tiles(plan, tdepth, 0); }
+
+int lope_batch_plan_get_tiles(const lope_batch_plan* plan, int32_t* tdepth, int32_t* rows) {
+    if (!plan || !tdepth || !rows) return fail(LOPE_ERR_INVALID_ARG, "null plan or output");
+    *tdepth = plan->tdepth;
+    *rows = plan->rows;
+    return LOPE_OK;
+}
+
+int lope_batch_tune_set(int32_t dtype, int64_t points, int32_t tdepth, int32_t rows) {
+    if (dtype != LOPE_F32 && dtype != LOPE_F64) return fail(LOPE_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    if (points < 1) return fail(LOPE_ERR_INVALID_ARG, "points %lld < 1", (long long)points);
+    if (tdepth < 0 || tdepth > kBatchMaxDepth)
+        return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 0..%d", tdepth, kBatchMaxDepth);
+    if (tdepth > 0 && (rows < 1 || rows > kBatchMaxRows))
+        return fail(LOPE_ERR_INVALID_ARG, "rows %d not in 1..%d", rows, kBatchMaxRows);
+    std::lock_guard<std::mutex> lk(g_batch_tune_mu);
+    const std::pair<int, int> key(dtype, log2_bucket(points));
+    if (tdepth == 0)
+        g_batch_tune.erase(key);
+    else
+        g_batch_tune[key] = std::make_pair((int)tdepth, (int)rows);
     return LOPE_OK;
 }
 
@@ -1123,11 +1245,12 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream) {
         e = enqueue_batch_passes(plan, s);
         return e == hipSuccess ? LOPE_OK : hip_fail(e, "batch pass launch");
     }
-    if (!plan->graph || plan->graph_depth != plan->tdepth) {
+    if (!plan->graph || plan->graph_depth != plan->tdepth || plan->graph_rows != plan->rows) {
         if (plan->graph) (void)hipGraphExecDestroy(plan->graph);
         plan->graph = nullptr;
         if ((e = record_batch_graph(plan, &plan->graph)) != hipSuccess) return hip_fail(e, "batch graph recording");
         plan->graph_depth = plan->tdepth;
+        plan->graph_rows = plan->rows;
     }
     e = hipGraphLaunch(plan->graph, s);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "batch graph launch");
@@ -1205,6 +1328,7 @@ int lope_tune_set(const lope_grid* g, const lope_stencil* st, const lope_tuning*
         return fail(LOPE_ERR_INVALID_ARG, "variant %d out of range", tune->variant);
     if (tune->rules != 0 && tune->rules != 1)
         return fail(LOPE_ERR_INVALID_ARG, "rules %d: 0 (every axis periodic) or 1 (some axis Dirichlet)", tune->rules);
+    if (tune->chunk < 0) return fail(LOPE_ERR_INVALID_ARG, "chunk %d < 0", tune->chunk);
     static thread_local SweepJob job;
     lope_bc bc{};
     for (int a = 0; a < 3; ++a) bc.kind[a] = tune->rules && a == 0 ? LOPE_BC_DIRICHLET : LOPE_BC_PERIODIC;

@@ -99,14 +99,14 @@ k_accumulate(DevGrid part, DevGrid total) {
     }
 }
 
-__global__ void k_zero_one(double* out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *out = 0.0;
-}
-
-// gbar = sum_x ybar[x] * sum_{taps o with x+o in a Dirichlet halo} c_o
+// gbar = sum_x ybar[x] * sum_{taps o with x+o in a Dirichlet halo} c_o, in
+// two passes with a fixed summation order (the same value on every run):
+// workgroup b sums its grid-stride share of the points per thread, then a
+// tree over its threads, into partials[b]; one workgroup then sums the
+// partials the same way.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_gbar(DevGrid y, DevRule rule, TapList<T> taps, double* out) {
+k_gbar_partial(DevGrid y, DevRule rule, TapList<T> taps, double* __restrict__ partials) {
     __shared__ double red[kThreads];
     const T* __restrict__ yp = (const T*)y.origin;
     const int64_t total = (int64_t)y.nx * y.ny * y.nz;
@@ -133,7 +133,23 @@ k_gbar(DevGrid y, DevRule rule, TapList<T> taps, double* out) {
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(out, red[0]);
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// *out = sum of partials[0 .. n), one workgroup.  Every read happens before
+// the first barrier and the one write after the last, so out may be
+// partials itself.
+__global__ void __launch_bounds__(kThreads) k_gbar_final(const double* partials, int n, double* out) {
+    __shared__ double red[kThreads];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) acc += partials[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
 }
 
 template <typename T>
@@ -219,16 +235,16 @@ hipError_t launch_accumulate(const DevGrid& part, int part_dtype, const DevGrid&
     return hipGetLastError();
 }
 
-hipError_t launch_gbar(const SweepJob& j, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(64), 0, s, out);
+hipError_t launch_gbar(const SweepJob& j, double* partials, double* out, hipStream_t s) {
     const int blocks = grid_blocks((int64_t)j.src.nx * j.src.ny * j.src.nz);
-    const int b = blocks > 1024 ? 1024 : blocks;
+    const int b = blocks > kGbarPartials ? kGbarPartials : blocks;
     if (j.dtype == LOPE_F32)
-        hipLaunchKernelGGL(k_gbar<float>, dim3(b), dim3(kThreads), 0, s, j.src, j.rule,
-                           make_taps<float>(j), out);
+        hipLaunchKernelGGL(k_gbar_partial<float>, dim3(b), dim3(kThreads), 0, s, j.src, j.rule, make_taps<float>(j),
+                           partials);
     else
-        hipLaunchKernelGGL(k_gbar<double>, dim3(b), dim3(kThreads), 0, s, j.src, j.rule,
-                           make_taps<double>(j), out);
+        hipLaunchKernelGGL(k_gbar_partial<double>, dim3(b), dim3(kThreads), 0, s, j.src, j.rule,
+                           make_taps<double>(j), partials);
+    hipLaunchKernelGGL(k_gbar_final, dim3(1), dim3(kThreads), 0, s, partials, b, out);
     return hipGetLastError();
 }
 

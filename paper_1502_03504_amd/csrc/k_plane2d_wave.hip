@@ -28,44 +28,48 @@ Coef9<T> coef9(const SweepJob& j) {
     return cf;
 }
 
-template <typename T, int TD, bool BOX, int NW, int STG>
-hipError_t launch_wave(const SweepJob& j, const Coef9<T>& cf, const Coef9<T>& cf2, T alpha, int chunk,
-                       hipStream_t s) {
+// One pass with the kernel built for rule case (DX, DY) and residual flag
+// RES.  The automatic row chunk: as long as the resident waves (at the
+// register use of this very build) still cover every chunk in few rounds.
+template <typename T, int TD, bool BOX, int NW, int STG, bool DX, bool DY, bool RES>
+hipError_t launch_wave_case(const SweepJob& j, const Coef9<T>& cf, const Coef9<T>& cf2, T alpha, int chunk,
+                            hipStream_t s) {
+    constexpr auto kernel = k_plane2d_wave<T, TD, BOX, NW, DX, DY, RES, STG>;
     const int out_cols = 64 - 2 * TD;
     const int strips = (j.src.nx + out_cols - 1) / out_cols;
-    // automatic row chunk: as long as the resident waves still cover every
-    // chunk in few rounds
     if (chunk <= 0) {
-        static const int bpc = blocks_per_cu(k_plane2d_wave<T, TD, BOX, NW, false, false, false, STG>, NW * 64);
+        static const int bpc = blocks_per_cu(kernel, NW * 64);
         chunk = balanced_chunk(strips, j.src.ny, (int64_t)device_cu_count() * bpc * NW, 2 * TD + 2, 2 * TD);
     }
     const int chunks = (j.src.ny + chunk - 1) / chunk;
     const int64_t nw64 = (int64_t)strips * chunks;
     if (nw64 > (1ll << 30)) return hipErrorInvalidConfiguration;
     const int nw = (int)nw64;
-    const int nb = (nw + NW - 1) / NW;
-    const int nbp = padded_block_count(nb);
+    const int nbp = padded_block_count((nw + NW - 1) / NW);
+    hipLaunchKernelGGL(kernel, dim3(nbp), dim3(NW * 64), 0, s, j.src, j.dst, j.rule, cf, cf2, alpha, chunk, strips,
+                       nw, nbp, j.residual);
+    return hipGetLastError();
+}
+
+template <typename T, int TD, bool BOX, int NW, int STG>
+hipError_t launch_wave(const SweepJob& j, const Coef9<T>& cf, const Coef9<T>& cf2, T alpha, int chunk,
+                       hipStream_t s) {
     const bool dx = !j.rule.per[0], dy = !j.rule.per[1];
-#define LOPE_WAVE_LAUNCH(A, B, C)                                                                                  \
-    hipLaunchKernelGGL((k_plane2d_wave<T, TD, BOX, NW, A, B, C, STG>), dim3(nbp), dim3(NW * 64), 0, s, j.src,     \
-                       j.dst, j.rule, cf, cf2, alpha, chunk, strips, nw, nbp, j.residual)
-#define LOPE_WAVE_RULE(C)                  \
-    if (dx && dy)                          \
-        LOPE_WAVE_LAUNCH(true, true, C);   \
-    else if (dx)                           \
-        LOPE_WAVE_LAUNCH(true, false, C);  \
-    else if (dy)                           \
-        LOPE_WAVE_LAUNCH(false, true, C);  \
-    else                                   \
-        LOPE_WAVE_LAUNCH(false, false, C)
+#define LOPE_WAVE_RULE(C)                                                                          \
+    if (dx && dy)                                                                                  \
+        return launch_wave_case<T, TD, BOX, NW, STG, true, true, C>(j, cf, cf2, alpha, chunk, s);   \
+    else if (dx)                                                                                   \
+        return launch_wave_case<T, TD, BOX, NW, STG, true, false, C>(j, cf, cf2, alpha, chunk, s);  \
+    else if (dy)                                                                                   \
+        return launch_wave_case<T, TD, BOX, NW, STG, false, true, C>(j, cf, cf2, alpha, chunk, s);  \
+    else                                                                                           \
+        return launch_wave_case<T, TD, BOX, NW, STG, false, false, C>(j, cf, cf2, alpha, chunk, s)
     if (STG == 0 && j.residual) {
         LOPE_WAVE_RULE(STG == 0);
     } else {
         LOPE_WAVE_RULE(false);
     }
 #undef LOPE_WAVE_RULE
-#undef LOPE_WAVE_LAUNCH
-    return hipGetLastError();
 }
 
 template <typename T, int TD, bool BOX, int NW>

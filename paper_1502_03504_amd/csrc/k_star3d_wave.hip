@@ -320,18 +320,20 @@ Coef7<T> coef7(const SweepJob& j) {
     return cf;
 }
 
-// One pass over j's grids (its rule and residual; the stencils in cf, cf2).
-template <typename T, int TD, int P, int NW, int PF, int WPE, int STG>
-hipError_t launch_wave3(const SweepJob& j, const Coef7<T>& cf, const Coef7<T>& cf2, T alpha, int chunk,
-                        hipStream_t s) {
+// One pass over j's grids with the kernel built for rule case (DXY, DZ) and
+// residual flag RES (the stencils in cf, cf2).  The automatic z-chunk: as
+// long as the resident waves (the workgroups a compute unit holds at the
+// register use of this very build, on every unit) still cover every chunk in
+// few rounds.
+template <typename T, int TD, int P, int NW, int PF, int WPE, int STG, bool DXY, bool DZ, bool RES>
+hipError_t launch_wave3_case(const SweepJob& j, const Coef7<T>& cf, const Coef7<T>& cf2, T alpha, int chunk,
+                             hipStream_t s) {
+    constexpr auto kernel = k_star3d_wave<T, TD, P, NW, DXY, DZ, RES, STG, PF, WPE>;
     const int out_cols = 64 - 2 * TD;
     const int strips = (j.src.nx + out_cols - 1) / out_cols;
     const int segs = (j.src.ny + P - 1) / P;
-    // automatic z-chunk: as long as the resident waves (the workgroups a
-    // compute unit holds at the compiled register use, on every unit) still
-    // cover every chunk in few rounds
     if (chunk <= 0) {
-        static const int bpc = blocks_per_cu(k_star3d_wave<T, TD, P, NW, false, false, false, STG, PF, WPE>, NW * 64);
+        static const int bpc = blocks_per_cu(kernel, NW * 64);
         chunk = balanced_chunk((int64_t)strips * segs, j.src.nz, (int64_t)device_cu_count() * bpc * NW, 2 * TD + 2,
                                2 * TD);
     }
@@ -340,27 +342,31 @@ hipError_t launch_wave3(const SweepJob& j, const Coef7<T>& cf, const Coef7<T>& c
     if (nw64 > (1ll << 30)) return hipErrorInvalidConfiguration;
     const int nw = (int)nw64;
     const int nbp = padded_block_count((nw + NW - 1) / NW);
+    hipLaunchKernelGGL(kernel, dim3(nbp), dim3(NW * 64), 0, s, j.src, j.dst, j.rule, cf, cf2, alpha, chunk, strips,
+                       segs, nw, nbp, j.residual);
+    return hipGetLastError();
+}
+
+// One pass over j's grids (its rule and residual; the stencils in cf, cf2).
+template <typename T, int TD, int P, int NW, int PF, int WPE, int STG>
+hipError_t launch_wave3(const SweepJob& j, const Coef7<T>& cf, const Coef7<T>& cf2, T alpha, int chunk,
+                        hipStream_t s) {
     const bool dxy = !j.rule.per[0] || !j.rule.per[1], dz = !j.rule.per[2];
-#define LOPE_WAVE3_LAUNCH(A, B, C)                                                                              \
-    hipLaunchKernelGGL((k_star3d_wave<T, TD, P, NW, A, B, C, STG, PF, WPE>), dim3(nbp), dim3(NW * 64), 0, s,    \
-                       j.src, j.dst, j.rule, cf, cf2, alpha, chunk, strips, segs, nw, nbp, j.residual)
-#define LOPE_WAVE3_RULE(C)                 \
-    if (dxy && dz)                         \
-        LOPE_WAVE3_LAUNCH(true, true, C);  \
-    else if (dxy)                          \
-        LOPE_WAVE3_LAUNCH(true, false, C); \
-    else if (dz)                           \
-        LOPE_WAVE3_LAUNCH(false, true, C); \
-    else                                   \
-        LOPE_WAVE3_LAUNCH(false, false, C)
+#define LOPE_WAVE3_RULE(C)                                                                         \
+    if (dxy && dz)                                                                                 \
+        return launch_wave3_case<T, TD, P, NW, PF, WPE, STG, true, true, C>(j, cf, cf2, alpha, chunk, s);   \
+    else if (dxy)                                                                                  \
+        return launch_wave3_case<T, TD, P, NW, PF, WPE, STG, true, false, C>(j, cf, cf2, alpha, chunk, s);  \
+    else if (dz)                                                                                   \
+        return launch_wave3_case<T, TD, P, NW, PF, WPE, STG, false, true, C>(j, cf, cf2, alpha, chunk, s);  \
+    else                                                                                           \
+        return launch_wave3_case<T, TD, P, NW, PF, WPE, STG, false, false, C>(j, cf, cf2, alpha, chunk, s)
     if (STG == 0 && j.residual) {
         LOPE_WAVE3_RULE(STG == 0);
     } else {
         LOPE_WAVE3_RULE(false);
     }
 #undef LOPE_WAVE3_RULE
-#undef LOPE_WAVE3_LAUNCH
-    return hipGetLastError();
 }
 
 template <typename T, int TD, int P, int NW, int PF, int WPE>

@@ -57,7 +57,11 @@ hipError_t launch_halo_fill(const DevGrid& g, const int lo[3], const int hi[3], 
                             hipStream_t s);
 hipError_t launch_accumulate(const DevGrid& part, int part_dtype, const DevGrid& total,
                              hipStream_t s);
-hipError_t launch_gbar(const SweepJob& j, double* out, hipStream_t s);
+// dL/dg of the adjoint (see lope_apply_adjoint) into *out, in a fixed order:
+// per-workgroup sums into partials[0 .. min(blocks, kGbarPartials)), then one
+// workgroup sums those (out may equal partials).
+constexpr int kGbarPartials = LOPE_GBAR_DOUBLES;
+hipError_t launch_gbar(const SweepJob& j, double* partials, double* out, hipStream_t s);
 // *out (device) = max over the interior of |y - x| in float64 (x, y same extents)
 hipError_t launch_residual_max(const DevGrid& x, const DevGrid& y, int dtype, double* out, hipStream_t s);
 // *out (device) = +0.0, the identity of the residual maximum

@@ -8,6 +8,10 @@ tdepth argument is 0.  Results are kept in a JSON cache keyed by
 (architecture, ndim, radius, dtype, star/box, size bucket = floor(log2 points),
 requested depth, boundary-rule class) and by variant NAME, so a cache
 survives rebuilds that renumber variants.
+Batch plans are tuned the same way: every (sweeps per launch, rows per strip)
+of a plan is timed and the fastest is registered for batches of its dtype and
+size bucket (floor(log2 of the batch's interior points)), with the cache key
+(architecture, "batch", dtype, bucket).
 Tuning runs off the timed path.
 """
 from __future__ import annotations
@@ -161,6 +165,14 @@ def register_cache(path=None) -> int:
     count = 0
     for key, v in cache.items():
         parts = key.split("|")
+        if len(parts) == 4 and parts[1] == "batch":
+            arch, _, dt, bucket = parts
+            if arch != ARCH:
+                continue
+            code = _lib.LOPE_F64 if dt == "f64" else _lib.LOPE_F32
+            if lib.lope_batch_tune_set(code, 1 << int(bucket), int(v["tdepth"]), int(v["rows"])) == 0:
+                count += 1
+            continue
         if len(parts) == 6:
             parts.append("0")
         if len(parts) == 7:
@@ -229,6 +241,71 @@ def _workloads():
     ]
 
 
+BATCH_ROWS = (32, 64, 128, 256)
+
+
+def batch_key(dtype_code, points):
+    bucket = int(math.floor(math.log2(points))) if points > 0 else 0
+    return "%s|batch|%s|%d" % (ARCH, "f64" if dtype_code == _lib.LOPE_F64 else "f32", bucket)
+
+
+def autotune_batch(plan, points, depths=range(1, 9), rows=BATCH_ROWS, repeats=3, register=True, cache_path=None,
+                   log=None):
+    """Time a batch plan's passes at every (sweeps per launch, rows per strip)
+    and register the fastest for batches of its dtype and size bucket (the
+    tiling lope_batch_plan_create then starts with).  Returns (best, results)."""
+    from . import lope_batch_tune_set
+    s = torch.cuda.current_stream()
+    results = []
+    for td in depths:
+        for r in rows:
+            plan.set_tiles(td, r)
+            plan.apply()              # records the plan's graph for this tiling
+            times = []
+            for _ in range(repeats):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                plan.apply()
+                e1.record(s)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1) * 1e-3)
+            t = sorted(times)[len(times) // 2]
+            rec = {"tdepth": td, "rows": r, "s": t, "gpts": points * plan.n_steps / t / 1e9}
+            results.append(rec)
+            if log:
+                log("batch tdepth=%d rows=%-4d %.3f ms %.1f GPt/s" % (td, r, t * 1e3, rec["gpts"]))
+    best = min(results, key=lambda r: r["s"])
+    dtype = plan.entries[0][0].dtype
+    if register:
+        lope_batch_tune_set(dtype, points, best["tdepth"], best["rows"])
+        if cache_path:
+            cache = load_cache_file(cache_path)
+            code = _lib.LOPE_F64 if dtype == torch.float64 else _lib.LOPE_F32
+            cache[batch_key(code, points)] = {"tdepth": best["tdepth"], "rows": best["rows"],
+                                              "gpts": round(best["gpts"], 2)}
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+    plan.set_tiles(best["tdepth"], best["rows"])
+    return best, results
+
+
+def _tune_batch_workload(path, log=None):
+    """The 512-grid batch of the benchmark (seeded synthetic grids)."""
+    import synth
+    from . import BatchPlan, Grid
+    grids, steps = synth.case_batch()
+    entries = [(Grid.from_array(g.field, 1), Grid.allocate(g.field.shape, 1, torch.float32), g.stencil, g.bc)
+               for g in grids]
+    points = sum(int(g.field.size) for g in grids)
+    plan = BatchPlan(entries, steps)
+    best, _ = autotune_batch(plan, points, cache_path=path, log=log)
+    plan.close()
+    del entries
+    torch.cuda.empty_cache()
+    return best
+
+
 def tune_workloads(path, names=None, log=None):
     """Time every fitting (variant, chunk) on the benchmark workloads and write
     the choices to the JSON table at `path`: replaced when every workload is
@@ -242,6 +319,12 @@ def tune_workloads(path, names=None, log=None):
                 kept = json.load(f)
         os.remove(path)
     out = {}
+    if not names or "batch" in names:
+        if log:
+            log("== batch")
+        out["batch"] = _tune_batch_workload(path, log=log)
+        if log:
+            log("best: %s" % out["batch"])
     for name, make, chunks in _workloads():
         if names and name not in names:
             continue

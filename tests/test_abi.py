@@ -428,3 +428,79 @@ def test_tune_cache_registration(tmp_path):
     assert L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 1) == names[t1]
     bad = _lib.lope_tuning(names[t2], 1, 0, 0)       # depth 1 request answered by a depth-2 variant
     assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(bad)) == _lib.LOPE_ERR_INVALID_ARG
+
+
+def _star7(centre=0.4, side=0.1):
+    s, keep = stencil(ndim=3, r=1, fill=0.0)
+    keep[13] = centre
+    for i in (4, 10, 12, 14, 16, 22):
+        keep[i] = side
+    return s, keep
+
+
+def _padded_grid(n, h=1):
+    """A descriptor laid out like Grid.allocate (128-byte rows)."""
+    sy = ((n[0] + 2 * h + 31) // 32) * 32 + 32
+    return grid(n=n, h=h, sy=sy, sz=sy * (n[1] + 2 * h))
+
+
+def test_untuned_size_takes_nearest_tuned_bucket():
+    """A size whose own bucket is not in the committed table takes the choice
+    of the nearest tuned bucket of its class (the committed 512^3 float32
+    periodic heat entries), so automatic requests keep a fused kernel."""
+    s, _keep = _star7()
+    buf = ctypes.create_string_buffer(256)
+    for n in ((256, 256, 256), (1024, 512, 512), (96, 80, 72)):
+        g = _padded_grid(n)
+        v = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 0)
+        assert v > 0
+        L.lope_variant_info(v, buf, 256)
+        depth = int(dict(kv.split("=") for kv in buf.value.decode().split()[1:])["tdepth"])
+        assert depth >= 2, (n, buf.value)
+    # an explicit depth is answered by the nearest bucket's choice of that depth
+    g = _padded_grid((256, 256, 256))
+    for req in (1, 2, 3, 4):
+        v = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, req)
+        L.lope_variant_info(v, buf, 256)
+        assert b"tdepth=%d " % req in buf.value, (req, buf.value)
+
+
+def test_tune_set_rejects_negative_chunk():
+    s, _keep = _star7()
+    g = _padded_grid((64, 64, 64))
+    v = L.lope_select_variant(ctypes.byref(g), ctypes.byref(s), None, 1)
+    bad = _lib.lope_tuning(v, 1, -3, 0)
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(bad)) == _lib.LOPE_ERR_INVALID_ARG
+    big = _lib.lope_tuning(v, 1, 2 ** 31 - 1, 0)     # clamped to the marched extent at launch
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(big)) == 0
+    clear = _lib.lope_tuning(0, 1, 0, 0)
+    assert L.lope_tune_set(ctypes.byref(g), ctypes.byref(s), ctypes.byref(clear)) == 0
+
+
+def test_gbar_size_matches_header():
+    import paper_1502_03504_amd as P
+    text = open(HEADER).read()
+    m = re.search(r"#define LOPE_GBAR_DOUBLES (\d+)", text)
+    assert m and int(m.group(1)) == P.LOPE_GBAR_DOUBLES
+
+
+def test_batch_tune_set_validation_and_cache(tmp_path):
+    import json
+    from paper_1502_03504_amd import tune
+    F32 = _lib.LOPE_F32
+    assert L.lope_batch_tune_set(7, 1 << 20, 4, 128) == _lib.LOPE_ERR_INVALID_ARG      # dtype
+    assert L.lope_batch_tune_set(F32, 0, 4, 128) == _lib.LOPE_ERR_INVALID_ARG          # points
+    assert L.lope_batch_tune_set(F32, 1 << 20, 9, 128) == _lib.LOPE_ERR_INVALID_ARG    # depth
+    assert L.lope_batch_tune_set(F32, 1 << 20, 4, 0) == _lib.LOPE_ERR_INVALID_ARG      # rows
+    assert L.lope_batch_tune_set(F32, 1 << 20, 4, 1 << 17) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_tune_set(F32, 1 << 20, 4, 64) == 0
+    assert L.lope_batch_tune_set(F32, 1 << 20, 0, 0) == 0                              # removes it
+    d, r = ctypes.c_int32(), ctypes.c_int32()
+    assert L.lope_batch_plan_get_tiles(None, ctypes.byref(d), ctypes.byref(r)) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_plan_set_tiles(None, 2, 64) == _lib.LOPE_ERR_INVALID_ARG
+    cache = {tune.batch_key(F32, 1 << 21): {"tdepth": 5, "rows": 64, "gpts": 1.0},
+             "other_arch|batch|f32|21": {"tdepth": 5, "rows": 64, "gpts": 1.0}}
+    path = tmp_path / "cache.json"
+    path.write_text(json.dumps(cache))
+    assert tune.register_cache(str(path)) == 1
+    assert L.lope_batch_tune_set(F32, 1 << 21, 0, 0) == 0

@@ -23,11 +23,10 @@ def _field(shape, dtype, seed):
     return rng.uniform(-1, 1, size=shape).astype(dtype)
 
 
-def _replay_matches(record, inputs, outputs, inexact=()):
+def _replay_matches(record, inputs, outputs):
     """record(): enqueue the calls under test.  inputs: (grid, array) pairs
-    reset before each run.  outputs(): host arrays of the results; those whose
-    index is in ``inexact`` are sums whose order varies between runs (atomic
-    adds of per-workgroup partials) and match to 1e-13 instead of exactly."""
+    reset before each run.  outputs(): host arrays of the results, which
+    every replay must reproduce exactly (reductions sum in a fixed order)."""
 
     def reset():
         for g, u in inputs:
@@ -52,10 +51,7 @@ def _replay_matches(record, inputs, outputs, inexact=()):
         torch.cuda.synchronize()
         got = outputs()
         for k, (x, y) in enumerate(zip(got, want)):
-            if k in inexact:
-                np.testing.assert_allclose(x, y, rtol=1e-13, atol=0, err_msg="replay %d output %d" % (rep, k))
-            else:
-                np.testing.assert_array_equal(x, y, err_msg="replay %d output %d" % (rep, k))
+            np.testing.assert_array_equal(x, y, err_msg="replay %d output %d" % (rep, k))
     del g
 
 
@@ -95,7 +91,7 @@ def test_iterate_2d_and_stages_captured():
 def test_adjoint_and_var_captured():
     y = _field((23, 31, 66), np.float64, 4)
     ya, xa = grid_from(y, 4), empty_grid(y.shape, 4, np.float64)
-    gbar = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    gbar = L.gbar_buffer()
     u = _field((20, 24, 65), np.float32, 5)
     kap = (0.5 + 0.25 * _field(u.shape, np.float32, 6)).astype(np.float32)
     ua, ub = grid_from(u, 1), empty_grid(u.shape, 1, np.float32)
@@ -107,9 +103,9 @@ def test_adjoint_and_var_captured():
         L.lope_apply_var(ua, ub, ka, 0.1, ((P, P, P), 0.0))
 
     def outputs():
-        return [xa.numpy(), gbar.cpu().numpy(), ub.numpy()]
+        return [xa.numpy(), gbar[:1].cpu().numpy(), ub.numpy()]
 
-    _replay_matches(record, [(ya, y), (ua, u)], outputs, inexact=(1,))
+    _replay_matches(record, [(ya, y), (ua, u)], outputs)
 
 
 def test_iterate_until_refuses_capture():

@@ -89,7 +89,7 @@ def test_every_variant_and_depth_agrees(ndim, r, shape_kind, dtype):
                 b = empty_grid(u.shape, r, dtype)
                 idx = L.lope_iterate_tuned(a, b, st, (kinds, 0.5), n, variant=vid, chunk=chunk)
                 got = (a, b)[idx].numpy()
-                assert rel_err(got, want) <= tol(dtype) * n, (info, chunk, kinds, rel_err(got, want))
+                assert rel_err(got, want) <= tol(dtype), (info, chunk, kinds, rel_err(got, want))
                 if ref is None:
                     ref = got
                 else:
@@ -118,7 +118,7 @@ def test_wave_brick_kernels_edge_shapes(shape):
         want = oracle.iterate(u, st.coeffs, kinds, 0.5, n)
         x, y = grid_from(u, 1), empty_grid(u.shape, 1, np.float32)
         ref = (x, y)[L.lope_iterate(x, y, st, (kinds, 0.5), n, tdepth=1)].numpy()
-        assert rel_err(ref, want) <= tol(np.float32) * n
+        assert rel_err(ref, want) <= tol(np.float32), rel_err(ref, want)
         for vid, info in waves:
             for chunk in (0, 1, 3):
                 a, b = grid_from(u, 1), empty_grid(u.shape, 1, np.float32)
@@ -143,7 +143,7 @@ def test_wave_kernels_tall_columns(shape, dtype, kind):
     want = oracle.iterate(u, st.coeffs, kinds, 0.5, n)
     x, y = grid_from(u, 1), empty_grid(u.shape, 1, dtype)
     ref = (x, y)[L.lope_iterate(x, y, st, (kinds, 0.5), n, tdepth=1)].numpy()
-    assert rel_err(ref, want) <= tol(dtype) * n
+    assert rel_err(ref, want) <= tol(dtype), rel_err(ref, want)
     waves = [(vid, info) for vid, info in variants_for(ndim, 1, dtype, shape=kind) if info.startswith(prefix)]
     assert waves
     for vid, info in waves:
@@ -178,7 +178,7 @@ def test_empty_and_degenerate_grids(dtype):
             b = empty_grid(u.shape, 1, dtype)
             idx = L.lope_iterate(a, b, st, (kinds, 0.7), 3)
             want = oracle.iterate(u, st.coeffs, kinds, 0.7, 3)
-            assert rel_err((a, b)[idx].numpy(), want) <= tol(dtype) * 3, (shape, kinds)
+            assert rel_err((a, b)[idx].numpy(), want) <= tol(dtype), (shape, kinds)
 
 
 def test_radius_zero_and_large_halo():
@@ -204,11 +204,15 @@ def test_adjoint_matches_oracle(ndim, r, shape_kind, dtype):
     for kinds in BCS[ndim]:
         a = grid_from(yb, r)
         b = empty_grid(yb.shape, r, dtype)
-        gb = torch.full((1,), 123.0, dtype=torch.float64, device="cuda")
+        gb = L.gbar_buffer(fill=123.0)
         L.lope_apply_adjoint(a, b, st, (kinds, 0.9), gbar=gb)
         xw, gw = oracle.adjoint(yb, st.coeffs, kinds)
         assert rel_err(b.numpy(), xw) <= tol(dtype), kinds
-        assert abs(gb.item() - gw) <= 1e-9 * max(1.0, abs(gw)), (gb.item(), gw)
+        assert abs(gb[0].item() - gw) <= 1e-9 * max(1.0, abs(gw)), (gb[0].item(), gw)
+        # the fixed summation order: a second run gives the same bits
+        again = L.gbar_buffer(fill=-5.0)
+        L.lope_apply_adjoint(a, b, st, (kinds, 0.9), gbar=again)
+        assert again[0].item() == gb[0].item()
 
 
 @pytest.mark.parametrize("packed", [False, True])
@@ -235,7 +239,8 @@ def test_diffusion_forward_and_reverse(dtype, packed):
         want_l = oracle.diffusion_step_transpose(lam, k, dt)
         want_g = 0.5 + oracle.diffusion_kappa_vjp(u, lam, dt)
         assert rel_err(lam_out.numpy(), want_l) <= tol(dtype)
-        assert rel_err(gk.numpy() - 0.5, want_g - 0.5) <= 10 * tol(gdt if gdt == np.float32 else dtype)
+        gtol = tol(gdt if gdt == np.float32 else dtype)   # the coarser of the two precisions
+        assert rel_err(gk.numpy() - 0.5, want_g - 0.5) <= gtol, rel_err(gk.numpy() - 0.5, want_g - 0.5)
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -250,7 +255,7 @@ def test_packed_grids_take_scalar_kernels(r, dtype):
         b = packed_grid_from(np.zeros_like(u), r)
         idx = L.lope_iterate(a, b, st, (kinds, 0.3), 3, tdepth=1)
         want = oracle.iterate(u, st.coeffs, kinds, 0.3, 3)
-        assert rel_err((a, b)[idx].numpy(), want) <= tol(dtype) * 3
+        assert rel_err((a, b)[idx].numpy(), want) <= tol(dtype)
 
 
 def test_accumulate():
@@ -289,7 +294,7 @@ def test_batch_matches_per_grid_and_oracle(dtype):
     got = [plan.result(i).numpy() for i in range(len(entries))]
     for i, (e, u) in enumerate(zip(entries, fields)):
         want = oracle.iterate(u, e[2].coeffs, e[3][0], e[3][1], n)
-        assert rel_err(got[i], want) <= tol(dtype) * n, i
+        assert rel_err(got[i], want) <= tol(dtype), (i, rel_err(got[i], want))
     # same grids through one launch per grid per sweep: identical values
     for (src, dst, _, _), u in zip(entries, fields):
         src.interior().copy_(torch.from_numpy(u).cuda())
@@ -324,7 +329,7 @@ def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
             ref = got
             for i, (e, u) in enumerate(zip(entries, fields)):
                 want = oracle.iterate(u, e[2].coeffs, e[3][0], e[3][1], n)
-                assert rel_err(got[i], want) <= tol(dtype) * n, i
+                assert rel_err(got[i], want) <= tol(dtype), (i, rel_err(got[i], want))
         else:
             for i in range(len(entries)):
                 np.testing.assert_array_equal(got[i], ref[i], err_msg="depth %d grid %d" % (depth, i))
