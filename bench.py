@@ -118,7 +118,7 @@ def measure_adjoint(n=256, steps=200, every=20):
             "ratio_end_to_end": round((t2 - t1) / (t1 - t0), 3)}
 
 
-def measure_batch(reps=3, per_grid=True):
+def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
     """512 uneven 2D float32 grids, 50 sweeps each: the batched launches against
     one launch per grid per sweep (median of reps, HIP events)."""
     import numpy as np
@@ -147,23 +147,26 @@ def measure_batch(reps=3, per_grid=True):
         ts.sort()
         return ts[len(ts) // 2]
 
-    by_depth = {}
-    for td in (1, 2, 3, 4, 5, 6, 7, 8):
-        plan.set_depth(td)
-        by_depth[td] = timed(plan.apply)
-    best = min(by_depth, key=by_depth.get)
-    plan.set_depth(best)
-    tb = by_depth[best]
+    # the plan's own tiling: the one the tuning table registers for this
+    # batch's dtype and size (what lope_batch_apply does by default)
+    depth, rows = plan.tiles()
+    tb = timed(plan.apply)
     tp = timed(plan.apply_per_grid) if per_grid else None
+    # context only: every depth at the plan's rows
+    by_depth = {}
+    if by_depth_sweep:
+        for td in range(1, 9):
+            plan.set_depth(td)
+            by_depth[td] = timed(plan.apply)
     plan.close()
     upd = points * steps
-    return {"workload": "batch_512_grids_2d_f32_50_sweeps", "points": points, "tdepth": best,
+    return {"workload": "batch_512_grids_2d_f32_50_sweeps", "points": points, "tdepth": depth, "rows": rows,
             "batched_ms": round(tb, 3), "per_grid_ms": round(tp, 3) if tp else None,
             "batched_GPts": round(upd / (tb * 1e-3) / 1e9, 1),
             "per_grid_GPts": round(upd / (tp * 1e-3) / 1e9, 1) if tp else None,
             "speedup": round(tp / tb, 2) if tp else None,
-            "batched_ms_by_depth": {str(k): round(v, 3) for k, v in by_depth.items()},
-            "launches_batched": -(-steps // best), "launches_per_grid": steps * len(grids)}
+            "batched_ms_by_depth": {str(k): round(v, 3) for k, v in by_depth.items()} or None,
+            "launches_batched": -(-steps // depth), "launches_per_grid": steps * len(grids)}
 
 
 def measure_copy(mib=1024, reps=10):
