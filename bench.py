@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+VALU_LANE_OPS = 256 * 64 * 2.4e9   # fp32 lane operations per second, one per clock per lane
 
 
 def log(*a):
@@ -73,23 +74,28 @@ def measure_adjoint(n=256, steps=200, every=20):
     g32 = L.Grid.allocate(c.u0.shape, 0, torch.float32)
     s = torch.cuda.current_stream()
 
-    def timed(fn, reps=20):
+    def timed(fn, reps=7, calls=20):
+        """Median over reps of the time per call of `calls` back-to-back calls
+        (the host-side checks of each call overlap the previous kernels, as
+        in the time loop of the gradient driver)."""
         fn()
         ts = []
         for _ in range(reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
-            fn()
+            for _ in range(calls):
+                fn()
             e1.record(s)
             e1.synchronize()
-            ts.append(e0.elapsed_time(e1))
+            ts.append(e0.elapsed_time(e1) / calls)
         ts.sort()
         return ts[len(ts) // 2]
 
     fwd = timed(lambda: L.lope_apply_var(u, v, kap, c.dt, bc))
-    adj1 = timed(lambda: L.lope_apply_var_adjoint(lam, lam2, u, kap, c.dt, bc, g32))
-    # the reverse sweep runs step pairs fused: per-step time = pass time / 2
-    adj = timed(lambda: L.lope_apply_var_adjoint2(lam, lam2, u, v, kap, c.dt, bc, g32)) / 2.0
+    # the reverse step the gradient driver runs (one step per call)
+    adj = timed(lambda: L.lope_apply_var_adjoint(lam, lam2, u, kap, c.dt, bc, g32))
+    # context: the fused two-step pass, per step
+    pair = timed(lambda: L.lope_apply_var_adjoint2(lam, lam2, u, v, kap, c.dt, bc, g32)) / 2.0
     u0 = torch.from_numpy(c.u0).cuda()
     k0 = torch.from_numpy(c.kappa).cuda()
     tg = torch.from_numpy(c.target).cuda()
@@ -110,10 +116,11 @@ def measure_adjoint(n=256, steps=200, every=20):
     return {"workload": "diffusion_7pt_varcoef_%d^3_f32_periodic_%d_steps_checkpoint_%d" % (n, steps, every),
             "fwd_ms_per_step": round(fwd, 4), "adj_ms_per_step": round(adj, 4),
             "ratio_per_step": round(adj / fwd, 3),
-            "adj_single_step_ms": round(adj1, 4), "ratio_single_step": round(adj1 / fwd, 3),
             "fwd_GBs": round(12.0 * pts / (fwd * 1e-3) / 1e9, 1),
-            "adj_pair_GBs": round(28.0 * pts / (2 * adj * 1e-3) / 1e9, 1),
-            "adj_single_GBs": round(24.0 * pts / (adj1 * 1e-3) / 1e9, 1),
+            "fwd_frac": round(12.0 * pts / (fwd * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "adj_GBs": round(24.0 * pts / (adj * 1e-3) / 1e9, 1),
+            "adj_frac": round(24.0 * pts / (adj * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "pair_ms_per_step": round(pair, 4), "pair_GBs": round(28.0 * pts / (2 * pair * 1e-3) / 1e9, 1),
             "fwd_total_ms": round((t1 - t0) * 1e3, 2), "bwd_total_ms": round((t2 - t1) * 1e3, 2),
             "ratio_end_to_end": round((t2 - t1) / (t1 - t0), 3)}
 
@@ -170,26 +177,38 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
 
 
 def measure_copy(mib=1024, reps=10):
-    """Context for the roofline: a plain device-to-device copy (torch's copy
-    kernel) of `mib` MiB, bytes read + written over its median time."""
+    """Attainable-bandwidth reference: the library's streaming copy kernel
+    (16-byte non-temporal loads and stores) over `mib` MiB, bytes read +
+    written over its median time; torch's copy kernel beside it for context."""
     import torch
+
+    import paper_1502_03504_amd as L
     n_el = mib * (1 << 20) // 4
     src = torch.ones(n_el, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     s = torch.cuda.current_stream()
-    dst.copy_(src)
-    ts = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        dst.copy_(src)
-        e1.record(s)
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    ms = sorted(ts)[reps // 2]
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[reps // 2]
+
+    ms = timed(lambda: L.lope_copy_stream(src, dst))
+    ok = bool(torch.equal(src, dst))
+    ms_t = timed(lambda: dst.copy_(src))
     del src, dst
     torch.cuda.empty_cache()
-    return {"MiB": mib, "ms": round(ms, 4), "GBs": round(2 * mib * (1 << 20) / (ms * 1e-3) / 1e9, 1)}
+    gbs = lambda t: round(2 * mib * (1 << 20) / (t * 1e-3) / 1e9, 1)
+    return {"MiB": mib, "kernel": "lope_copy_stream (16-byte non-temporal)", "ms": round(ms, 4), "GBs": gbs(ms),
+            "frac": round(gbs(ms) / PEAK_HBM_GBS, 4), "copied_exactly": ok,
+            "torch_copy_ms": round(ms_t, 4), "torch_copy_GBs": gbs(ms_t)}
 
 
 def measure_workloads(reps=3):
@@ -203,26 +222,29 @@ def measure_workloads(reps=3):
     import paper_1502_03504_amd as L
     import synth
 
-    cases = [("heat2d_5pt_256^2_f64_dirichlet_100_sweeps", synth.case_heat2d),
-             ("heat3d_7pt_256^3_f64_periodic_1000_sweeps", lambda: synth.case_heat3d(n=256, dtype=np.float64)),
-             ("box9_8192^2_f32_periodic_1000_sweeps", synth.case_box9),
-             ("star25_r4_512^3_f32_dirichlet_500_sweeps", synth.case_star25)]
+    # (name, inputs, sweeps per pass requested: 0 = the tuned default)
+    cases = [("heat3d_7pt_512^3_f32_periodic_1000_sweeps_one_sweep_per_pass",
+              lambda: synth.case_heat3d(n=512, dtype=np.float32), 1),
+             ("heat2d_5pt_256^2_f64_dirichlet_100_sweeps", synth.case_heat2d, 0),
+             ("heat3d_7pt_256^3_f64_periodic_1000_sweeps", lambda: synth.case_heat3d(n=256, dtype=np.float64), 0),
+             ("box9_8192^2_f32_periodic_1000_sweeps", synth.case_box9, 0),
+             ("star25_r4_512^3_f32_dirichlet_500_sweeps", synth.case_star25, 0)]
     out = {}
     s = torch.cuda.current_stream()
-    for name, make in cases:
+    for name, make, td in cases:
         case = make()
         a = L.Grid.from_array(case.field, case.h)
         b = a.empty_like()
         pts, esize = int(case.field.size), case.field.dtype.itemsize
         case = case._replace(field=None)
-        vid = L.lope_select_variant(a, case.stencil, 0, bc=case.bc)
+        vid = L.lope_select_variant(a, case.stencil, td, bc=case.bc)
         info = L.lope_variant_info(vid) if vid > 0 else "generic"
-        L.lope_iterate(a, b, case.stencil, case.bc, case.steps)
+        L.lope_iterate(a, b, case.stencil, case.bc, case.steps, tdepth=td)
         ts = []
         for _ in range(reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
-            L.lope_iterate(a, b, case.stencil, case.bc, case.steps)
+            L.lope_iterate(a, b, case.stencil, case.bc, case.steps, tdepth=td)
             e1.record(s)
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
@@ -231,10 +253,73 @@ def measure_workloads(reps=3):
         out[name] = {"ms": round(ms, 3), "GPts": round(upd / 1e9, 1),
                      "effective_GBs": round(upd * 2 * esize / 1e9, 1),
                      "frac": round(upd * 2 * esize / 1e9 / PEAK_HBM_GBS, 4), "kernel": info.split()[0]}
+        if name.startswith("star25"):
+            # both ceilings of one sweep per pass: HBM at 8 algorithmic bytes
+            # per point-update; VALU at 25 fmas per point-update on 256 CUs x
+            # 64 fp32 lanes per clock x 2.4 GHz (no packed fp32)
+            taps = int(np.count_nonzero(case.stencil.coeffs))
+            out[name]["ceilings_GPts"] = {"hbm_peak": round(PEAK_HBM_GBS / (2 * esize), 1),
+                                          "valu": round(VALU_LANE_OPS / taps / 1e9, 1), "taps": taps}
         log("workload:", name, out[name])
         del a, b
         torch.cuda.empty_cache()
     return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(field, st, bc, sweeps, n, threads=None):
+    """The oracle's sweep timed on the host: `sweeps` full-size sweeps on one
+    core, and as many again on slabs of planes run by a thread pool (numpy
+    releases the GIL inside each slab's arithmetic; each slab carries one
+    plane of its neighbours on each side, wrapped periodically, and keeps its
+    own planes of the result)."""
+    import concurrent.futures
+
+    import numpy as np
+
+    import oracle
+    t = time.perf_counter()
+    u = field
+    for _ in range(sweeps):
+        u = oracle.sweep(u, st.coeffs, bc.kinds, 0.0)
+    one = time.perf_counter() - t
+    threads = threads or max(1, min(16, os.cpu_count() or 1))
+    nz = field.shape[0]
+    bounds = [(k * nz // threads, (k + 1) * nz // threads) for k in range(threads)]
+
+    def slab(u, z0, z1, out):
+        idx = [z % nz for z in range(z0 - 1, z1 + 1)]
+        res = oracle.sweep(u[idx], st.coeffs, bc.kinds, 0.0)
+        out[z0:z1] = res[1:-1]
+
+    t = time.perf_counter()
+    v = field
+    with concurrent.futures.ThreadPoolExecutor(threads) as ex:
+        for _ in range(sweeps):
+            w = np.empty_like(v)
+            list(ex.map(lambda b: slab(v, b[0], b[1], w), bounds))
+            v = w
+    many = time.perf_counter() - t
+    same = bool(np.array_equal(u, v))
+    pts = n ** 3
+    return {"value": pts * sweeps / one / 1e9, "unit": "GPoint-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full-size sweeps of the %d^3 float32 grid (numpy, float64 arithmetic, single-threaded), "
+                      "%.1f s" % (sweeps, n, one),
+            "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
+            "all_cores": {"value": pts * sweeps / many / 1e9, "cores": threads,
+                          "sample": "the same sweeps on %d z-slabs run by %d threads, %.1f s (result identical "
+                                    "to the single-threaded run: %s)" % (threads, threads, many, same)}}
 
 
 def main():
@@ -247,7 +332,7 @@ def main():
     ap.add_argument("--tdepth", type=int, default=0, help="sweeps fused per pass (0 = library default)")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--cpu-sweeps", type=int, default=2, help="full-size oracle sweeps timed (0 = skip)")
+    ap.add_argument("--cpu-sweeps", type=int, default=3, help="full-size oracle sweeps timed (0 = skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -383,16 +468,7 @@ def main():
 
     cpu = None
     if args.cpu_sweeps > 0:
-        import oracle
-        t = time.perf_counter()
-        u = field_cpu
-        for _ in range(args.cpu_sweeps):
-            u = oracle.sweep(u, st.coeffs, bc.kinds, 0.0)
-        el = time.perf_counter() - t
-        cpu = {"value": pts * args.cpu_sweeps / el / 1e9, "unit": "GPoint-updates/s", "cores": 1,
-               "kind": "oracle",
-               "sample": "%d full-size sweeps of the %d^3 float32 grid (numpy, float64 arithmetic, "
-                         "single-threaded), %.1f s" % (args.cpu_sweeps, n, el)}
+        cpu = cpu_baseline(field_cpu, st, bc, args.cpu_sweeps, n)
 
     out = {
         "metric": "GPoint-updates/s, 3D 7-point heat stencil, 512^3 float32, periodic",

@@ -189,8 +189,9 @@ int lope_apply(const lope_grid* src, const lope_grid* dst, const lope_stencil* s
 /* n_steps sweeps alternating between a and b (section 3.2, the loop around
  * the sweep and the halo transfer; double buffering per section 2.2).  The
  * initial state is a's interior.  Several sweeps may be fused per pass over
- * memory: tdepth 1..4 asks for that many, 0 lets the tuning table choose
- * (possibly more than 4); the result is identical.  *result_index is
+ * memory: tdepth 1..4 asks for that many (fewer where no kernel fuses that
+ * many for this grid and stencil, e.g. radius 2-4), 0 lets the tuning table
+ * choose (possibly more than 4); the result is identical.  *result_index is
  * set to 0 if the final state is in a, 1 if in b (n_steps mod 2 when one
  * sweep runs per pass).  Both grids' halos must cover the stencil's reach.
  * result_index must not be NULL. */
@@ -377,6 +378,16 @@ int lope_batch_result_index(const lope_batch_plan* plan, int32_t* out);
 /* Release the plan's device memory (the caller synchronises first if the plan
  * may still be running).  NULL is a no-op. */
 int lope_batch_plan_destroy(lope_batch_plan* plan);
+
+/* ---- measurement aid ---------------------------------------------------------- */
+
+/* Copies `bytes` bytes from src to dst (device pointers, 16-byte aligned,
+ * bytes a multiple of 16, the ranges not overlapping, each inside one
+ * device allocation) with 16-byte non-temporal loads and stores: the
+ * attainable-bandwidth reference for the sweeps' roofline figures (not part
+ * of the method).  Asynchronous on `stream`.  Misaligned or overlapping
+ * arguments give LOPE_ERR_INVALID_ARG. */
+int lope_copy_stream(const void* src, void* dst, int64_t bytes, void* stream);
 
 /* ---- introspection --------------------------------------------------------- */
 

@@ -26,7 +26,8 @@ __all__ = [
     "gbar_buffer", "LOPE_GBAR_DOUBLES", "lope_apply_var", "lope_apply_var_adjoint",
     "lope_accumulate", "lope_variant_count", "lope_variant_info", "lope_select_variant",
     "lope_tune_set", "variants", "BatchPlan", "lope_batch_plan_create", "lope_batch_apply",
-    "lope_batch_apply_per_grid", "lope_batch_plan_destroy", "lope_batch_tune_set", "DIRICHLET", "PERIODIC",
+    "lope_batch_apply_per_grid", "lope_batch_plan_destroy", "lope_batch_tune_set",
+    "lope_copy_stream", "DIRICHLET", "PERIODIC",
 ]
 
 DIRICHLET = "dirichlet"
@@ -322,6 +323,16 @@ def lope_iterate_stages(a: Grid, b: Grid, first, second, alpha: float, bc, n_ste
 
 
 LOPE_GBAR_DOUBLES = 1024   # doubles of the array lope_apply_adjoint's gbar points to
+
+
+def lope_copy_stream(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """dst <- src (contiguous device tensors of equal byte size, a multiple of
+    16 bytes) with the library's streaming copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_contiguous() and dst.is_contiguous()) or dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("contiguous tensors of equal byte size")
+    check(load().lope_copy_stream(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                  _stream(stream)))
 
 
 def gbar_buffer(device="cuda", fill=0.0) -> torch.Tensor:

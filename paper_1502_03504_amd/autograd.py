@@ -9,28 +9,26 @@ returns dL/du0 and dL/dkappa:
   checkpoint_every), so memory grows with n_steps / k, not n_steps;
 * the backward pass walks the segments in reverse; for each it recomputes the
   segment's states from its checkpoint with the forward kernel, then runs the
-  reverse kernels from the segment's last step down to its first, which turn
-  lambda_{t+1} = dL/du_{t+1} into lambda_t and add each step's kappa
-  derivative into a float32 accumulator.  Steps (2m+1, 2m) that lie in one
-  segment run as one fused two-step pass (lope_apply_var_adjoint2), the rest
-  one step at a time;
+  one-step reverse kernel (lope_apply_var_adjoint) from the segment's last
+  step down to its first, which turns lambda_{t+1} = dL/du_{t+1} into
+  lambda_t and adds the step's kappa derivative into an accumulator;
 * every FOLD_EVERY steps (at t divisible by it) the float32 accumulator is
   folded into a float64 total (lope_accumulate), so the kappa gradient is
-  reduced in float64 over the time loop.
+  reduced in float64 over the time loop.  For float64 states the reverse
+  kernels add each step's terms straight into the float64 total.
 
-Recomputation is deterministic (same kernels, same inputs), the fused pass
-computes every lambda_t exactly as the one-step kernel does, and the folds sit
-at fixed time indices.  So dL/du0 is bit-for-bit independent of the
-checkpoint interval; dL/dkappa is too for every even interval (all pairs
-fused), while an odd interval splits some pairs and changes only the rounding
-of the kappa accumulator.  Everything runs on the current
-stream; nothing synchronises with the host.
+Recomputation is deterministic (same kernels, same inputs) and the folds sit
+at fixed time indices, so both gradients are bit-for-bit independent of the
+checkpoint interval.  (lope_apply_var_adjoint2, two reverse steps in one
+pass, moves fewer bytes per step but runs slower per step than the one-step
+wave kernel on this device, so the driver does not use it.)  Everything runs
+on the current stream; nothing synchronises with the host.
 """
 from __future__ import annotations
 
 import torch
 
-from . import Grid, lope_accumulate, lope_apply_var, lope_apply_var_adjoint, lope_apply_var_adjoint2
+from . import Grid, lope_accumulate, lope_apply_var, lope_apply_var_adjoint
 
 _PERIODIC = (("periodic",) * 3, 0.0)
 FOLD_EVERY = 20
@@ -72,8 +70,11 @@ class DiffusionFunction(torch.autograd.Function):
         lam = Grid.allocate(shape, 1, grad_out.dtype, dev)
         lam.interior().copy_(grad_out)
         lam2 = Grid.allocate(shape, 1, grad_out.dtype, dev)
-        g32 = Grid.allocate(shape, 0, torch.float32, dev)
         g64 = Grid.allocate(shape, 0, torch.float64, dev)
+        # float32 states: per-step terms in a float32 partial, folded into g64;
+        # float64 states: straight into g64
+        fold = grad_out.dtype != torch.float64
+        gacc = Grid.allocate(shape, 0, torch.float32, dev) if fold else g64
         seg_states = [Grid.allocate(shape, 1, grad_out.dtype, dev) for _ in range(min(k, n))]
         for s in range(len(checkpoints) - 1, -1, -1):
             t0 = s * k
@@ -82,21 +83,11 @@ class DiffusionFunction(torch.autograd.Function):
             seg_states[0].interior().copy_(checkpoints[s].interior())
             for i in range(1, length):
                 lope_apply_var(seg_states[i - 1], seg_states[i], kap, dt, _PERIODIC)
-            i = length - 1
-            while i >= 0:
-                t = t0 + i
-                if t % 2 == 1 and i >= 1:
-                    # steps t and t-1 fused (pairs sit at absolute indices (2m+1, 2m))
-                    lope_apply_var_adjoint2(lam, lam2, seg_states[i], seg_states[i - 1], kap, dt, _PERIODIC, g32)
-                    low = t - 1
-                    i -= 2
-                else:
-                    lope_apply_var_adjoint(lam, lam2, seg_states[i], kap, dt, _PERIODIC, g32)
-                    low = t
-                    i -= 1
+            for i in range(length - 1, -1, -1):
+                lope_apply_var_adjoint(lam, lam2, seg_states[i], kap, dt, _PERIODIC, gacc)
                 lam, lam2 = lam2, lam
-                if low % FOLD_EVERY == 0:
-                    lope_accumulate(g32, g64)
+                if fold and (t0 + i) % FOLD_EVERY == 0:
+                    lope_accumulate(gacc, g64)
         grad_u0 = lam.interior().clone()
         grad_kappa = g64.interior().to(grad_out.dtype)
         return grad_u0, grad_kappa, None, None, None

@@ -311,8 +311,6 @@ struct Registry {
         const Variant* p;
         int n = star3d_vec_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
-        n = star3d_vtb_variants(&p);
-        for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = star3d_variants(&p);
         for (int i = 0; i < n; ++i) v.push_back(p[i]);
         n = star3d_flat_variants(&p);
@@ -596,6 +594,146 @@ struct PlanGrid {
     lope_stencil st;
 };
 
+// Byte span of one interior of a batch: [lo, hi), the item and which buffer.
+struct BatchSpan {
+    uintptr_t lo, hi;
+    int64_t item;
+    int dst;
+};
+
+// Structural, device and memory checks of a batch (before anything is
+// allocated or enqueued); *dtype receives the batch's element type.  Every
+// pass writes one buffer of every item while it reads the other, so the
+// interiors of all 2 n_items buffers must be disjoint: their spans are sorted
+// into `spans` (room for 2 n_items entries) and neighbours compared.
+int batch_check(const lope_batch_item* items, int64_t n_items, int64_t n_steps, int* dtype, BatchSpan* spans) {
+    int rc;
+    if (!items && n_items > 0) return fail(LOPE_ERR_INVALID_ARG, "null item array");
+    if (n_items < 0 || n_items > (1 << 20)) return fail(LOPE_ERR_INVALID_ARG, "n_items %lld out of range", (long long)n_items);
+    if (n_steps < 0 || n_steps > (1 << 24)) return fail(LOPE_ERR_INVALID_ARG, "n_steps %lld out of range", (long long)n_steps);
+    *dtype = n_items > 0 ? items[0].src.dtype : LOPE_F32;
+    for (int64_t i = 0; i < n_items; ++i) {
+        const lope_batch_item& it = items[i];
+        char a[32], b[32];
+        snprintf(a, sizeof a, "items[%lld].src", (long long)i);
+        snprintf(b, sizeof b, "items[%lld].dst", (long long)i);
+        if ((rc = check_grid(&it.src, a)) || (rc = check_grid(&it.dst, b)) || (rc = check_same(&it.src, &it.dst, a, b)) ||
+            (rc = check_bc(&it.bc, it.src.ndim)) || (rc = check_stencil(&it.stencil, it.src.ndim, nullptr)))
+            return rc;
+        if (it.src.ndim != 2) return fail(LOPE_ERR_UNSUPPORTED, "%s: batches hold 2D grids", a);
+        if (it.src.dtype != *dtype) return fail(LOPE_ERR_INVALID_ARG, "%s: all grids of a batch share one dtype", a);
+        if (it.stencil.radius > 1) return fail(LOPE_ERR_UNSUPPORTED, "%s: batch stencils have radius <= 1", a);
+        if ((rc = check_reach(&it.src, &it.stencil, false, a)) || (rc = check_reach(&it.dst, &it.stencil, false, b)))
+            return rc;
+        if ((rc = check_alias(&it.src, &it.dst, a, b))) return rc;
+    }
+    for (int64_t i = 0; i < n_items; ++i) {
+        for (int d = 0; d < 2; ++d) {
+            BatchSpan& sp = spans[2 * i + d];
+            span(d ? &items[i].dst : &items[i].src, false, &sp.lo, &sp.hi);
+            sp.item = i;
+            sp.dst = d;
+        }
+    }
+    std::sort(spans, spans + 2 * n_items, [](const BatchSpan& x, const BatchSpan& y) {
+        return x.lo < y.lo || (x.lo == y.lo && (x.item < y.item || (x.item == y.item && x.dst < y.dst)));
+    });
+    for (int64_t k = 0; k + 1 < 2 * n_items; ++k) {
+        const BatchSpan &x = spans[k], &y = spans[k + 1];
+        if (x.lo < x.hi && y.lo < y.hi && y.lo < x.hi)
+            return fail(LOPE_ERR_ALIAS, "items[%lld].%s and items[%lld].%s overlap (every grid of a batch needs "
+                        "buffers of its own)", (long long)x.item, x.dst ? "dst" : "src", (long long)y.item,
+                        y.dst ? "dst" : "src");
+    }
+    if ((rc = device_ready())) return rc;
+    for (int64_t i = 0; i < n_items; ++i) {
+        if ((rc = check_memory(&items[i].src, "batch src")) || (rc = check_memory(&items[i].dst, "batch dst"))) return rc;
+    }
+    return LOPE_OK;
+}
+
+// The kernel's descriptor of one grid: views, rule, the 3x3 coefficient table
+// rounded to the grid dtype, star or box.  `job` is working storage.
+void batch_grid_desc(const lope_grid* src, const lope_grid* dst, const lope_stencil* st, const lope_bc* bc,
+                     SweepJob& job, BatchGrid& bg) {
+    build_job(job, src, dst, st, bc, false);
+    bg = BatchGrid{};
+    bg.src = dev_grid(src);
+    bg.dst = dev_grid(dst);
+    bg.rule = dev_rule(bc, 2, false);
+    const int r = st->radius;
+    for (int oy = -r; oy <= r; ++oy)
+        for (int ox = -r; ox <= r; ++ox) bg.c[(ox + 1) + (oy + 1) * 3] = job.dense[(ox + r) + (oy + r) * (2 * r + 1)];
+    bg.box = job.star ? 0 : 1;
+}
+
+// Grids in tile-table order: dealt to the 8 XCD ranges largest first, each to
+// the least-loaded range, then listed range by range, so a grid's tiles get
+// consecutive workgroup ids (one XCD).  order and sorted hold n entries,
+// range holds n (working storage; nothing is allocated).
+void batch_order(const lope_batch_item* items, int64_t n, int64_t* order, int64_t* sorted, int8_t* range) {
+    auto points = [&](int64_t i) { return items[i].src.n[0] * items[i].src.n[1]; };
+    for (int64_t i = 0; i < n; ++i) sorted[i] = i;
+    std::sort(sorted, sorted + n, [&](int64_t x, int64_t y) {
+        return points(x) > points(y) || (points(x) == points(y) && x < y);
+    });
+    int64_t load[kNumXcd] = {};
+    for (int64_t k = 0; k < n; ++k) {
+        int best = 0;
+        for (int q = 1; q < kNumXcd; ++q)
+            if (load[q] < load[best]) best = q;
+        range[sorted[k]] = (int8_t)best;
+        load[best] += points(sorted[k]);
+    }
+    int64_t m = 0;
+    for (int q = 0; q < kNumXcd; ++q)
+        for (int64_t k = 0; k < n; ++k)
+            if (range[sorted[k]] == q) order[m++] = sorted[k];
+}
+
+// Work-table entries of passes of `depth` sweeps: per grid in `order`, strips
+// of batch_strip_width(depth) output columns by chunks of `rows` rows.  Writes
+// the first `cap` entries to out (if not null) and returns how many there are.
+int64_t batch_strips(const lope_batch_item* items, const int64_t* order, int64_t n, int depth, int rows,
+                     BatchItem* out, int64_t cap) {
+    const int64_t bw = batch_strip_width(depth);
+    int64_t count = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t gi = order[k];
+        const int64_t nx = items[gi].src.n[0], ny = items[gi].src.n[1];
+        if (nx == 0 || ny == 0) continue;
+        for (int64_t y0 = 0; y0 < ny; y0 += rows)
+            for (int64_t x0 = 0; x0 < nx; x0 += bw) {
+                if (out && count < cap) {
+                    BatchItem& it = out[count];
+                    it = BatchItem{};
+                    it.grid = (int32_t)gi;
+                    it.x0 = (int32_t)x0;
+                    it.y0 = (int32_t)y0;
+                    it.y1 = (int32_t)std::min(ny, y0 + rows);
+                }
+                ++count;
+            }
+    }
+    return count;
+}
+
+// Passes of n_steps sweeps at `depth` per launch on stream s: full passes
+// alternating src->dst and dst->src, then one pass of the remaining sweeps.
+hipError_t enqueue_passes(const BatchGrid* grids, const BatchItem* full_items, int n_full_items,
+                          const BatchItem* rem_items, int n_rem_items, int64_t n_steps, int depth, int dtype,
+                          hipStream_t s) {
+    const int64_t full = n_steps / depth;
+    const int rem = (int)(n_steps % depth);
+    int64_t pass = 0;
+    for (; pass < full; ++pass) {
+        const hipError_t e = launch_batch_pass(grids, full_items, n_full_items, depth, (int)(pass & 1), dtype, s);
+        if (e != hipSuccess) return e;
+    }
+    if (rem) return launch_batch_pass(grids, rem_items, n_rem_items, rem, (int)(pass & 1), dtype, s);
+    return hipSuccess;
+}
+
 }  // namespace
 
 struct lope_batch_plan {
@@ -605,6 +743,7 @@ struct lope_batch_plan {
     int tdepth = kBatchDefaultDepth;
     int rows = kBatchRows;            // rows per strip of the tile tables
     std::vector<PlanGrid> grids;
+    std::vector<lope_batch_item> items;   // the items as given, coefficients pointing into grids[i].coeffs
     std::vector<int64_t> order;       // grids in tile-table order (largest first, dealt to XCD ranges)
     std::vector<SweepJob> jobs;       // per-grid launches (the comparison path)
     std::vector<int> job_variant;
@@ -636,23 +775,11 @@ int plan_items(lope_batch_plan* p, int depth) {
         (void)hipFree(p->d_items[depth]);
         p->d_items[depth] = nullptr;
     }
-    std::vector<BatchItem> items;
-    const int64_t bw = batch_strip_width(depth), rows = p->rows;
-    for (int64_t gi : p->order) {
-        const lope_grid& g = p->grids[(size_t)gi].src;
-        const int64_t nx = g.n[0], ny = g.n[1];
-        if (nx == 0 || ny == 0) continue;
-        for (int64_t y0 = 0; y0 < ny; y0 += rows)
-            for (int64_t x0 = 0; x0 < nx; x0 += bw) {
-                BatchItem it{};
-                it.grid = (int32_t)gi;
-                it.x0 = (int32_t)x0;
-                it.y0 = (int32_t)y0;
-                it.y1 = (int32_t)std::min(ny, y0 + rows);
-                items.push_back(it);
-            }
-    }
-    if (items.size() > (size_t)(1 << 30)) return fail(LOPE_ERR_UNSUPPORTED, "batch tile table too long");
+    const int64_t n = (int64_t)p->order.size();
+    const int64_t count = batch_strips(p->items.data(), p->order.data(), n, depth, p->rows, nullptr, 0);
+    if (count > (int64_t)(1 << 30)) return fail(LOPE_ERR_UNSUPPORTED, "batch tile table too long");
+    std::vector<BatchItem> items((size_t)count);
+    batch_strips(p->items.data(), p->order.data(), n, depth, p->rows, items.data(), count);
     p->nitems[depth] = (int)items.size();
     p->items_rows[depth] = p->rows;
     if (items.empty()) return LOPE_OK;
@@ -677,16 +804,9 @@ int64_t plan_passes(const lope_batch_plan* p) {
 // Every pass of lope_batch_apply on stream s: full passes of tdepth sweeps
 // alternating src->dst and dst->src, then the remainder pass.
 hipError_t enqueue_batch_passes(const lope_batch_plan* p, hipStream_t s) {
-    const int64_t full = p->n_steps / p->tdepth;
     const int rem = (int)(p->n_steps % p->tdepth);
-    int64_t pass = 0;
-    for (; pass < full; ++pass) {
-        const hipError_t e = launch_batch_pass(p->d_grids, p->d_items[p->tdepth], p->nitems[p->tdepth], p->tdepth,
-                                               (int)(pass & 1), p->dtype, s);
-        if (e != hipSuccess) return e;
-    }
-    if (rem) return launch_batch_pass(p->d_grids, p->d_items[rem], p->nitems[rem], rem, (int)(pass & 1), p->dtype, s);
-    return hipSuccess;
+    return enqueue_passes(p->d_grids, p->d_items[p->tdepth], p->nitems[p->tdepth], rem ? p->d_items[rem] : nullptr,
+                          rem ? p->nitems[rem] : 0, p->n_steps, p->tdepth, p->dtype, s);
 }
 
 // Records the passes once into an executable graph (kernel nodes only) on a
@@ -982,8 +1102,11 @@ int lope_apply_var(const lope_grid* src, const lope_grid* dst, const lope_varcoe
     if ((rc = check_memory(src, "src")) || (rc = check_memory(dst, "dst")) || (rc = check_memory(vc->kappa, "kappa")))
         return rc;
     if (is_empty(src)) return LOPE_OK;
-    const hipError_t e = launch_var_forward(dev_grid(src), dev_grid(dst), dev_grid(vc->kappa), src->dtype, vc->dt,
-                                            (hipStream_t)stream);
+    const DevGrid gs = dev_grid(src), gd = dev_grid(dst), gk = dev_grid(vc->kappa);
+    const int es = (int)elem_size(src->dtype);
+    const hipError_t e = var_wave_fits(gs, es) && var_wave_fits(gd, es) && var_wave_fits(gk, es)
+                             ? launch_var_forward_wave(gs, gd, gk, src->dtype, vc->dt, (hipStream_t)stream)
+                             : launch_var_forward(gs, gd, gk, src->dtype, vc->dt, (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion launch");
 }
 
@@ -1016,9 +1139,14 @@ int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, cons
         (rc = check_memory(gkappa, "gkappa")))
         return rc;
     if (is_empty(lam_next)) return LOPE_OK;
-    const hipError_t e = launch_var_adjoint(dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(vc->kappa),
-                                            dev_grid(gkappa), lam_next->dtype, gkappa->dtype, vc->dt,
-                                            (hipStream_t)stream);
+    const DevGrid gn = dev_grid(lam_next), gl = dev_grid(lam), gu = dev_grid(u_t), gk = dev_grid(vc->kappa),
+                  gg = dev_grid(gkappa);
+    const int es = (int)elem_size(lam_next->dtype);
+    const bool wave = var_wave_fits(gn, es) && var_wave_fits(gl, es) && var_wave_fits(gu, es) &&
+                      var_wave_fits(gk, es) && var_wave_fits(gg, (int)elem_size(gkappa->dtype));
+    const hipError_t e =
+        wave ? launch_var_adjoint_wave(gn, gl, gu, gk, gg, lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream)
+             : launch_var_adjoint(gn, gl, gu, gk, gg, lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion adjoint launch");
 }
 
@@ -1077,31 +1205,13 @@ int lope_accumulate(const lope_grid* partial, const lope_grid* total, void* stre
 
 int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_t n_steps, void* stream,
                            lope_batch_plan** out) {
-    int rc;
+    int rc, dtype = LOPE_F32;
     if (!out) return fail(LOPE_ERR_INVALID_ARG, "null plan output");
     *out = nullptr;
-    if (!items && n_items > 0) return fail(LOPE_ERR_INVALID_ARG, "null item array");
     if (n_items < 0 || n_items > (1 << 20)) return fail(LOPE_ERR_INVALID_ARG, "n_items %lld out of range", (long long)n_items);
-    if (n_steps < 0 || n_steps > (1 << 24)) return fail(LOPE_ERR_INVALID_ARG, "n_steps %lld out of range", (long long)n_steps);
-    int dtype = n_items > 0 ? items[0].src.dtype : LOPE_F32;
-    for (int64_t i = 0; i < n_items; ++i) {
-        const lope_batch_item& it = items[i];
-        char a[32], b[32];
-        snprintf(a, sizeof a, "items[%lld].src", (long long)i);
-        snprintf(b, sizeof b, "items[%lld].dst", (long long)i);
-        if ((rc = check_grid(&it.src, a)) || (rc = check_grid(&it.dst, b)) || (rc = check_same(&it.src, &it.dst, a, b)) ||
-            (rc = check_bc(&it.bc, it.src.ndim)) || (rc = check_stencil(&it.stencil, it.src.ndim, nullptr)))
-            return rc;
-        if (it.src.ndim != 2) return fail(LOPE_ERR_UNSUPPORTED, "%s: batches hold 2D grids", a);
-        if (it.src.dtype != dtype) return fail(LOPE_ERR_INVALID_ARG, "%s: all grids of a batch share one dtype", a);
-        if (it.stencil.radius > 1) return fail(LOPE_ERR_UNSUPPORTED, "%s: batch stencils have radius <= 1", a);
-        if ((rc = check_reach(&it.src, &it.stencil, false, a)) || (rc = check_reach(&it.dst, &it.stencil, false, b)))
-            return rc;
-        if ((rc = check_alias(&it.src, &it.dst, a, b))) return rc;
-    }
-    if ((rc = device_ready())) return rc;
-    for (int64_t i = 0; i < n_items; ++i) {
-        if ((rc = check_memory(&items[i].src, "batch src")) || (rc = check_memory(&items[i].dst, "batch dst"))) return rc;
+    {
+        std::vector<BatchSpan> spans((size_t)(2 * n_items));
+        if ((rc = batch_check(items, n_items, n_steps, &dtype, spans.data()))) return rc;
     }
     lope_batch_plan* p = new lope_batch_plan();
     p->dtype = dtype;
@@ -1114,6 +1224,7 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
     (void)hipGetDevice(&p->device);
     // copy items (the stencil table is copied; grids are borrowed)
     p->grids.resize((size_t)n_items);
+    p->items.resize((size_t)n_items);
     for (int64_t i = 0; i < n_items; ++i) {
         PlanGrid& g = p->grids[(size_t)i];
         g.src = items[i].src;
@@ -1123,6 +1234,7 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         g.coeffs.assign(items[i].stencil.coeffs, items[i].stencil.coeffs + w * w);
         g.st = items[i].stencil;
         g.st.coeffs = g.coeffs.data();
+        p->items[(size_t)i] = lope_batch_item{g.src, g.dst, g.st, g.bc};
     }
     // per-grid jobs for the one-launch-per-grid path
     p->jobs.resize((size_t)n_items);
@@ -1132,38 +1244,19 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         build_job(p->jobs[(size_t)i], &g.src, &g.dst, &g.st, &g.bc, false);
         p->job_variant[(size_t)i] = default_variant(p->jobs[(size_t)i], 1);
     }
-    // grids dealt to the 8 XCD ranges largest-first, least-loaded; the tile
-    // tables list grids range by range, so a grid's tiles get consecutive
-    // workgroup ids (one XCD range)
-    std::vector<int64_t> order((size_t)n_items);
-    for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
-    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-        return items[x].src.n[0] * items[x].src.n[1] > items[y].src.n[0] * items[y].src.n[1];
-    });
-    std::vector<std::vector<int64_t>> qgrids(kNumXcd);
-    std::vector<int64_t> load(kNumXcd, 0);
-    for (int64_t i : order) {
-        int best = 0;
-        for (int q = 1; q < kNumXcd; ++q)
-            if (load[q] < load[best]) best = q;
-        qgrids[best].push_back(i);
-        load[best] += items[i].src.n[0] * items[i].src.n[1];
+    p->order.resize((size_t)n_items);
+    {
+        std::vector<int64_t> sorted((size_t)n_items);
+        std::vector<int8_t> range((size_t)n_items);
+        batch_order(p->items.data(), n_items, p->order.data(), sorted.data(), range.data());
     }
-    for (int q = 0; q < kNumXcd; ++q)
-        for (int64_t i : qgrids[q]) p->order.push_back(i);
     std::vector<BatchGrid> hg((size_t)n_items);
-    for (int64_t i = 0; i < n_items; ++i) {
-        const PlanGrid& g = p->grids[(size_t)i];
-        const SweepJob& j = p->jobs[(size_t)i];
-        BatchGrid& bg = hg[(size_t)i];
-        bg = BatchGrid{};
-        bg.src = dev_grid(&g.src);
-        bg.dst = dev_grid(&g.dst);
-        bg.rule = dev_rule(&g.bc, 2, false);
-        const int r = g.st.radius;
-        for (int oy = -r; oy <= r; ++oy)
-            for (int ox = -r; ox <= r; ++ox) bg.c[(ox + 1) + (oy + 1) * 3] = j.dense[(ox + r) + (oy + r) * (2 * r + 1)];
-        bg.box = j.star ? 0 : 1;
+    {
+        static thread_local SweepJob job;
+        for (int64_t i = 0; i < n_items; ++i) {
+            const PlanGrid& g = p->grids[(size_t)i];
+            batch_grid_desc(&g.src, &g.dst, &g.st, &g.bc, job, hg[(size_t)i]);
+        }
     }
     hipError_t e = hipMalloc(&p->d_grids, (hg.empty() ? 1 : hg.size()) * sizeof(BatchGrid));
     if (e == hipSuccess && !hg.empty())
@@ -1279,6 +1372,22 @@ int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream) {
 int lope_batch_plan_destroy(lope_batch_plan* plan) {
     plan_free(plan);
     return LOPE_OK;
+}
+
+int lope_copy_stream(const void* src, void* dst, int64_t bytes, void* stream) {
+    if (!src || !dst) return fail(LOPE_ERR_INVALID_ARG, "null pointer");
+    if (bytes < 0 || bytes % 16) return fail(LOPE_ERR_INVALID_ARG, "bytes %lld: a non-negative multiple of 16", (long long)bytes);
+    if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(LOPE_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+    if (bytes > 0 && a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes)
+        return fail(LOPE_ERR_ALIAS, "source and destination ranges overlap");
+    int rc;
+    if ((rc = device_ready())) return rc;
+    if (bytes == 0) return LOPE_OK;
+    if ((rc = check_device_pointer(src, (size_t)bytes, "src")) || (rc = check_device_pointer(dst, (size_t)bytes, "dst")))
+        return rc;
+    const hipError_t e = launch_copy16(src, dst, bytes, (hipStream_t)stream);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "copy launch");
 }
 
 const char* lope_status_string(int status) {

@@ -1,0 +1,390 @@
+// Variable-coefficient diffusion on a periodic 3D grid, one wavefront per
+// brick: the forward step and the one-step reverse.
+//
+//   forward:  u'_x = u_x + dt * sum_q K_q (u_q - u_x),   K_q = (kappa_x + kappa_q) / 2
+//   reverse:  lam_x = lam'_x + dt * sum_q K_q (lam'_q - lam'_x)
+//             gk_x += dt/2 * sum_q (u_q - u_x) (lam'_x - lam'_q)
+// with q over the six face neighbours in the order x-, x+, y-, y+, z-, z+.
+//
+// A wave owns 64 consecutive x columns (one per lane, all 64 are outputs) by
+// P rows and marches a z-chunk.  Each lane keeps its column's P + 2 rows of
+// the current plane in registers (the y neighbours are the rows above and
+// below).  The x neighbours come from lanes l-1 and l+1 by DPP lane shifts;
+// the two columns just outside the wave (x0 - 1 for lane 0, x0 + 64 for lane
+// 63) arrive in one extra load per plane and array: lane i < P loads the left
+// outside column of row i + 1, lane 32 + i the right one, and the row's shift
+// takes its outside value from there (read into a scalar register).  Every
+// index is wrapped (the grids are periodic), so lanes past a ragged x end
+// hold wrapped columns that are never stored.
+//
+// The z direction is the march: when plane j arrives its in-plane terms
+// (x-, x+, y-, y+) start its sums; then the face between planes j-1 and j is
+// evaluated once and added to both sides (plane j's z- term and plane j-1's
+// z+ term are the same products with opposite signs, exactly), which
+// completes plane j-1.  Per point the terms are therefore summed in the
+// order x-, x+, y-, y+, z-, z+ with one fma each, the same chain as the
+// one-thread-per-point LDS kernels.
+//
+// Loads and stores go through a buffer resource per plane: the plane base in
+// scalar registers, the column offset in one VGPR, the row offset as the
+// scalar offset (the caller checks plane sizes below 2^31 bytes).
+#include "lope_internal.h"
+
+namespace lope {
+namespace {
+
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+__device__ __forceinline__ Rsrc plane_rsrc(const void* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Raw-bit loads and stores through a plane's buffer resource.
+template <typename T>
+__device__ __forceinline__ T bload(Rsrc r, unsigned voff, int soff);
+template <>
+__device__ __forceinline__ float bload<float>(Rsrc r, unsigned voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(Rsrc r, unsigned voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, Rsrc r, unsigned voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, Rsrc r, unsigned voff, int soff) {
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) B64;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, v), r, (int)voff, soff, 0);
+}
+
+// DPP lane shifts over the whole wave (bound_ctrl off: a lane whose source
+// lies past the wave's end keeps `old`): from_left gives lane l the value of
+// lane l-1 (lane 0: old), from_right the value of lane l+1 (lane 63: old).
+constexpr int kWaveShr1 = 0x138, kWaveShl1 = 0x130;
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v, float old) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                                                 CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v, double old) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// The value lane `src` holds (wave-uniform).
+__device__ __forceinline__ float lane_value(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double lane_value(double v, int src) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Where a wave's brick sits and how this lane addresses one array.
+struct Brick {
+    int x0, y0, z0, zend;
+};
+
+__device__ __forceinline__ bool brick_of(const DevGrid& g, int P, int chunk, int strips, int segs, int nwaves,
+                                         int nbp, int nw_per_block, Brick& b) {
+    const int wave = xcd_logical_block(nbp) * nw_per_block + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wave >= nwaves) return false;
+    const int tx = wave % strips, rest = wave / strips;
+    b.x0 = tx * 64;
+    b.y0 = (rest % segs) * P;
+    b.z0 = (rest / segs) * chunk;
+    b.zend = min(b.z0 + chunk, g.nz);
+    return true;
+}
+
+// One array's addressing: column byte offset of this lane, byte offset of
+// this lane's outside column (see the file comment), wave-uniform row byte
+// offsets, plane bytes.
+template <typename T, int NR>
+struct Cols {
+    const char* base;
+    int64_t pbytes;
+    unsigned xo, eo;
+    int row[NR];
+    __device__ __forceinline__ void init(const DevGrid& g, const Brick& b, int P) {
+        const int lane = threadIdx.x & 63;
+        base = (const char*)g.origin;
+        pbytes = g.sz * (int64_t)sizeof(T);
+        xo = (unsigned)wrap_index(b.x0 + lane, g.nx) * (unsigned)sizeof(T);
+        const int i = lane & 31;
+        const int ecol = wrap_index(lane < 32 ? b.x0 - 1 : b.x0 + 64, g.nx);
+        const int erow = wrap_index(b.y0 + (i < P ? i : 0), g.ny);
+        eo = ((unsigned)erow * (unsigned)g.sy + (unsigned)ecol) * (unsigned)sizeof(T);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) row[r] = (int)((unsigned)wrap_index(b.y0 - 1 + r, g.ny) * (unsigned)g.sy * (unsigned)sizeof(T));
+    }
+    // rows 0 .. NR-1 of plane q (wrapped) into v, the outside columns into e
+    __device__ __forceinline__ void load(int q, int nz, T (&v)[NR], T& e) const {
+        const Rsrc rs = plane_rsrc(base + (int64_t)wrap_index(q, nz) * pbytes, pbytes);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = bload<T>(rs, xo, row[r]);
+        e = bload<T>(rs, eo, 0);
+    }
+};
+
+// x- and x+ neighbours of row r (1..P) of a plane held as (v, e)
+template <typename T, int NR>
+__device__ __forceinline__ void x_neighbours(const T (&v)[NR], T e, int r, T& left, T& right) {
+    left = lane_shift<kWaveShr1>(v[r], lane_value(e, r - 1));
+    right = lane_shift<kWaveShl1>(v[r], lane_value(e, 32 + r - 1));
+}
+
+template <typename T, int P, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strips, int segs, int nwaves, int nbp) {
+    constexpr int NR = P + 2;
+    Brick b;
+    if (!brick_of(src, P, chunk, strips, segs, nwaves, nbp, NW, b)) return;
+    Cols<T, NR> cu, ck;
+    cu.init(src, b, P);
+    ck.init(kap, b, P);
+    const int lane = threadIdx.x & 63;
+    const int nz = src.nz, ny = src.ny;
+    const int64_t dpb = dst.sz * (int64_t)sizeof(T);
+    const bool xin = b.x0 + lane < src.nx;   // lanes past a ragged x end store nothing
+    const unsigned so = (unsigned)(b.x0 + lane) * (unsigned)sizeof(T);
+    const T half = (T)0.5;
+
+    T u[2][NR], k[2][NR], eu[2], ek[2];   // current plane and the one in flight
+    T pu[P], pk[P], acc[P];               // plane j-1: centre values and its partial sums
+    const int jstart = b.z0 - 1, jend = b.zend;
+    cu.load(jstart, nz, u[0], eu[0]);
+    ck.load(jstart, nz, k[0], ek[0]);
+
+    auto step = [&](int j, auto cur_c) __attribute__((always_inline)) {
+        constexpr int C = decltype(cur_c)::value, N = C ^ 1;
+        if (j + 1 <= jend) {
+            cu.load(j + 1, nz, u[N], eu[N]);
+            ck.load(j + 1, nz, k[N], ek[N]);
+        }
+        const T(&U)[NR] = u[C];
+        const T(&K)[NR] = k[C];
+        T a[P];
+        const bool own = j >= b.z0 && j < b.zend;   // plane j is one of the brick's outputs
+        if (own) {   // its in-plane terms
+#pragma unroll
+            for (int r = 1; r <= P; ++r) {
+                const T uc = U[r], kc = K[r];
+                T ul, ur, kl, kr;
+                x_neighbours(U, eu[C], r, ul, ur);
+                x_neighbours(K, ek[C], r, kl, kr);
+                T s = (T)0;
+                s = fma(half * (kc + kl), ul - uc, s);
+                s = fma(half * (kc + kr), ur - uc, s);
+                s = fma(half * (kc + K[r - 1]), U[r - 1] - uc, s);
+                s = fma(half * (kc + K[r + 1]), U[r + 1] - uc, s);
+                a[r - 1] = s;
+            }
+        }
+        if (j > jstart) {
+            // the face between planes j-1 and j: plane j's z- term, and plane
+            // j-1's z+ term, which completes it
+            const bool done = j - 1 >= b.z0;
+            const Rsrc rd = plane_rsrc((const char*)dst.origin + (int64_t)(j - 1) * dpb, dpb);
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                const T w = half * (pk[r] + K[r + 1]);
+                const T d = U[r + 1] - pu[r];
+                const int y = b.y0 + r;
+                if (done && y < ny && xin)
+                    bstore(fma(dt, fma(w, d, acc[r]), pu[r]), rd, so, (int)((unsigned)y * (unsigned)dst.sy * (unsigned)sizeof(T)));
+                if (own) a[r] = fma(w, -d, a[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            pu[r] = U[r + 1];
+            pk[r] = K[r + 1];
+            acc[r] = own ? a[r] : (T)0;
+        }
+    };
+    int j = jstart;
+    for (; j + 1 <= jend; j += 2) {
+        step(j, std::integral_constant<int, 0>{});
+        step(j + 1, std::integral_constant<int, 1>{});
+    }
+    if (j <= jend) step(j, std::integral_constant<int, 0>{});
+}
+
+template <typename T, typename TG, int P, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, T dt, int chunk, int strips, int segs,
+               int nwaves, int nbp) {
+    constexpr int NR = P + 2;
+    Brick b;
+    if (!brick_of(lnext, P, chunk, strips, segs, nwaves, nbp, NW, b)) return;
+    Cols<T, NR> cl, cu, ck;
+    cl.init(lnext, b, P);
+    cu.init(ug, b, P);
+    ck.init(kap, b, P);
+    const int lane = threadIdx.x & 63;
+    const int nz = lnext.nz, ny = lnext.ny;
+    const bool xin = b.x0 + lane < lnext.nx;   // lanes past a ragged x end store nothing
+    const unsigned so = (unsigned)(b.x0 + lane) * (unsigned)sizeof(T);
+    const unsigned sg = (unsigned)(b.x0 + lane) * (unsigned)sizeof(TG);
+    const int64_t lpb = lam.sz * (int64_t)sizeof(T), gpb = gk.sz * (int64_t)sizeof(TG);
+    const T half = (T)0.5, hdt = (T)0.5 * dt;
+
+    T l[2][NR], u[2][NR], k[2][NR], el[2], eu[2], ek[2];
+    T pl[P], pu[P], pk[P], al[P], ag[P];
+    TG gold[P];   // kappa gradient of plane j-1, read one step ahead
+    const int jstart = b.z0 - 1, jend = b.zend;
+    cl.load(jstart, nz, l[0], el[0]);
+    cu.load(jstart, nz, u[0], eu[0]);
+    ck.load(jstart, nz, k[0], ek[0]);
+#pragma unroll
+    for (int r = 0; r < P; ++r) gold[r] = (TG)0;
+
+    auto step = [&](int j, auto cur_c) __attribute__((always_inline)) {
+        constexpr int C = decltype(cur_c)::value, N = C ^ 1;
+        if (j + 1 <= jend) {
+            cl.load(j + 1, nz, l[N], el[N]);
+            cu.load(j + 1, nz, u[N], eu[N]);
+            ck.load(j + 1, nz, k[N], ek[N]);
+        }
+        const T(&L)[NR] = l[C];
+        const T(&U)[NR] = u[C];
+        const T(&K)[NR] = k[C];
+        T a[P], g[P];
+        TG gnew[P];
+        const bool own = j >= b.z0 && j < b.zend;   // plane j is one of the brick's outputs
+        if (own) {
+            // its kappa gradient (read now, updated when the plane completes)
+            // and its in-plane terms
+            const Rsrc rgj = plane_rsrc((const char*)gk.origin + (int64_t)j * gpb, gpb);
+#pragma unroll
+            for (int r = 1; r <= P; ++r) {
+                const int y = b.y0 + r - 1;
+                gnew[r - 1] = y < ny && xin ? bload<TG>(rgj, sg, (int)((unsigned)y * (unsigned)gk.sy * (unsigned)sizeof(TG))) : (TG)0;
+                const T lc = L[r], uc = U[r], kc = K[r];
+                T ll, lr, ul, ur, kl, kr;
+                x_neighbours(L, el[C], r, ll, lr);
+                x_neighbours(U, eu[C], r, ul, ur);
+                x_neighbours(K, ek[C], r, kl, kr);
+                T s = (T)0, t = (T)0;
+                s = fma(half * (kc + kl), ll - lc, s);
+                t = fma(ul - uc, lc - ll, t);
+                s = fma(half * (kc + kr), lr - lc, s);
+                t = fma(ur - uc, lc - lr, t);
+                s = fma(half * (kc + K[r - 1]), L[r - 1] - lc, s);
+                t = fma(U[r - 1] - uc, lc - L[r - 1], t);
+                s = fma(half * (kc + K[r + 1]), L[r + 1] - lc, s);
+                t = fma(U[r + 1] - uc, lc - L[r + 1], t);
+                a[r - 1] = s;
+                g[r - 1] = t;
+            }
+        }
+        if (j > jstart) {
+            // the face between planes j-1 and j (both sides' terms are the same
+            // products with opposite signs); plane j-1 completes
+            const bool done = j - 1 >= b.z0;
+            const Rsrc rl = plane_rsrc((const char*)lam.origin + (int64_t)(j - 1) * lpb, lpb);
+            const Rsrc rg = plane_rsrc((const char*)gk.origin + (int64_t)(j - 1) * gpb, gpb);
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                const T w = half * (pk[r] + K[r + 1]);
+                const T dl = L[r + 1] - pl[r];   // lam'_j - lam'_{j-1}
+                const T du = U[r + 1] - pu[r];   // u_j - u_{j-1}
+                const int y = b.y0 + r;
+                if (done && y < ny && xin) {
+                    bstore(fma(dt, fma(w, dl, al[r]), pl[r]), rl, so, (int)((unsigned)y * (unsigned)lam.sy * (unsigned)sizeof(T)));
+                    bstore(gold[r] + (TG)(hdt * fma(du, -dl, ag[r])), rg, sg,
+                           (int)((unsigned)y * (unsigned)gk.sy * (unsigned)sizeof(TG)));
+                }
+                if (own) {
+                    a[r] = fma(w, -dl, a[r]);
+                    g[r] = fma(-du, dl, g[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            pl[r] = L[r + 1];
+            pu[r] = U[r + 1];
+            pk[r] = K[r + 1];
+            al[r] = own ? a[r] : (T)0;
+            ag[r] = own ? g[r] : (T)0;
+            gold[r] = own ? gnew[r] : (TG)0;
+        }
+    };
+    int j = jstart;
+    for (; j + 1 <= jend; j += 2) {
+        step(j, std::integral_constant<int, 0>{});
+        step(j + 1, std::integral_constant<int, 1>{});
+    }
+    if (j <= jend) step(j, std::integral_constant<int, 0>{});
+}
+
+// Bricks of 64 columns by P rows; the z-chunk balanced against the waves the
+// device holds at once for this very build (as the sweep kernels do).
+template <typename K>
+bool wave_geometry(K kernel, int nw_per_block, int P, const DevGrid& g, int& chunk, int& strips, int& segs, int& nw,
+                   int& nbp) {
+    strips = (g.nx + 63) / 64;
+    segs = (g.ny + P - 1) / P;
+    static const int bpc = blocks_per_cu(kernel, nw_per_block * 64);
+    // at least 16 planes per chunk: each chunk re-reads the plane before and
+    // after it, and these kernels are bound by memory traffic, not by the
+    // march's start-up
+    chunk = balanced_chunk((int64_t)strips * segs, g.nz, (int64_t)device_cu_count() * bpc * nw_per_block, 2, 16);
+    const int64_t w = (int64_t)strips * segs * ((g.nz + chunk - 1) / chunk);
+    if (w > ((int64_t)1 << 30)) return false;
+    nw = (int)w;
+    nbp = padded_block_count((nw + nw_per_block - 1) / nw_per_block);
+    return true;
+}
+
+constexpr int kVarNW = 4;
+constexpr int kFwdP32 = 8, kFwdP64 = 4, kAdjP32 = 6, kAdjP64 = 4;
+
+template <typename T, int P>
+hipError_t fwd(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, double dt, hipStream_t s) {
+    constexpr auto kernel = k_varw_forward<T, P, kVarNW>;
+    int chunk, strips, segs, nw, nbp;
+    if (!wave_geometry(kernel, kVarNW, P, src, chunk, strips, segs, nw, nbp)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(kernel, dim3(nbp), dim3(kVarNW * 64), 0, s, src, dst, kappa, (T)dt, chunk, strips, segs, nw, nbp);
+    return hipGetLastError();
+}
+
+template <typename T, typename TG, int P>
+hipError_t adj(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, const DevGrid& kappa, const DevGrid& gk,
+               double dt, hipStream_t s) {
+    constexpr auto kernel = k_varw_adjoint<T, TG, P, kVarNW>;
+    int chunk, strips, segs, nw, nbp;
+    if (!wave_geometry(kernel, kVarNW, P, lam_next, chunk, strips, segs, nw, nbp)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(kernel, dim3(nbp), dim3(kVarNW * 64), 0, s, lam_next, lam, u, kappa, gk, (T)dt, chunk, strips,
+                       segs, nw, nbp);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool var_wave_fits(const DevGrid& g, int esize) { return g.sz * (int64_t)esize < ((int64_t)1 << 31); }
+
+hipError_t launch_var_forward_wave(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, int dtype, double dt,
+                                   hipStream_t s) {
+    if (dtype == LOPE_F32) return fwd<float, kFwdP32>(src, dst, kappa, dt, s);
+    return fwd<double, kFwdP64>(src, dst, kappa, dt, s);
+}
+
+hipError_t launch_var_adjoint_wave(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, const DevGrid& kappa,
+                                   const DevGrid& gk, int dtype, int gk_dtype, double dt, hipStream_t s) {
+    if (dtype == LOPE_F32 && gk_dtype == LOPE_F32) return adj<float, float, kAdjP32>(lam_next, lam, u, kappa, gk, dt, s);
+    if (dtype == LOPE_F32) return adj<float, double, kAdjP32>(lam_next, lam, u, kappa, gk, dt, s);
+    if (gk_dtype == LOPE_F64) return adj<double, double, kAdjP64>(lam_next, lam, u, kappa, gk, dt, s);
+    return adj<double, float, kAdjP64>(lam_next, lam, u, kappa, gk, dt, s);
+}
+
+}  // namespace lope

@@ -67,6 +67,9 @@ hipError_t launch_residual_max(const DevGrid& x, const DevGrid& y, int dtype, do
 // *out (device) = +0.0, the identity of the residual maximum
 hipError_t launch_residual_zero(double* out, hipStream_t s);
 
+// Streaming copy of `bytes` (a multiple of 16; 16-byte aligned pointers).
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
+
 // Tuned kernel families.
 enum Family {
     FAM_GENERIC = 0,
@@ -107,7 +110,6 @@ int star3d_variants(const Variant** out);
 int star3d_flat_variants(const Variant** out);
 int star3d_wave_variants(const Variant** out);
 int star3d_vec_variants(const Variant** out);
-int star3d_vtb_variants(const Variant** out);
 int plane2d_variants(const Variant** out);
 int plane2d_wave_variants(const Variant** out);
 
@@ -117,6 +119,15 @@ hipError_t launch_var_forward(const DevGrid& src, const DevGrid& dst, const DevG
 hipError_t launch_var_adjoint(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u,
                               const DevGrid& kappa, const DevGrid& gk, int dtype, int gk_dtype,
                               double dt, hipStream_t s);
+
+// The same two steps with one wavefront per brick (64 columns, all outputs),
+// for grids whose planes hold fewer than 2^31 bytes (var_wave_fits); the
+// arithmetic per point is the same chain of fmas as the kernels above.
+bool var_wave_fits(const DevGrid& g, int esize);
+hipError_t launch_var_forward_wave(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, int dtype, double dt,
+                                   hipStream_t s);
+hipError_t launch_var_adjoint_wave(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, const DevGrid& kappa,
+                                   const DevGrid& gk, int dtype, int gk_dtype, double dt, hipStream_t s);
 
 // Two fused reverse steps: lam_{t-1} from lam_{t+1}, both kappa terms in one update.
 hipError_t launch_var_adjoint2(const DevGrid& lam_next, const DevGrid& lam_out, const DevGrid& u_t,

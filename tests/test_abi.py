@@ -217,6 +217,36 @@ def test_batch_validation():
     assert L.lope_batch_plan_destroy(None) == _lib.LOPE_OK
 
 
+def test_batch_buffers_shared_across_items_rejected():
+    """Every pass writes one buffer of every item while reading the other, so
+    a buffer overlapping another item's buffer is an alias (checked on the
+    host before the device is touched)."""
+    s2, _k = stencil(ndim=2, r=1)
+    it = (_lib.lope_batch_item * 3)()
+    base = [0x100000, 0x200000, 0x300000, 0x400000, 0x500000, 0x600000]
+    for i in range(3):
+        it[i].src = grid(ndim=2, origin=base[2 * i])
+        it[i].dst = grid(ndim=2, origin=base[2 * i + 1])
+        it[i].stencil = s2
+        it[i].bc = bc()
+    out = ctypes.c_void_p()
+    assert L.lope_batch_plan_create(it, 3, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_NO_DEVICE
+    it[2].dst = grid(ndim=2, origin=base[0] + 4 * 20)      # inside item 0's src interior
+    assert L.lope_batch_plan_create(it, 3, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_ALIAS
+    assert b"items[0].src" in L.lope_last_error() and b"items[2].dst" in L.lope_last_error()
+    it[2].dst = grid(ndim=2, origin=base[5])
+    it[1].src = grid(ndim=2, origin=base[4])               # the same buffer as item 2's src
+    assert L.lope_batch_plan_create(it, 3, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_ALIAS
+
+
+def test_copy_stream_validation():
+    assert L.lope_copy_stream(None, ctypes.c_void_p(0x1000), 16, None) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_copy_stream(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 17, None) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_copy_stream(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 16, None) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_copy_stream(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1010), 64, None) == _lib.LOPE_ERR_ALIAS
+    assert L.lope_copy_stream(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 64, None) == _lib.LOPE_ERR_NO_DEVICE
+
+
 def test_status_strings_and_variants():
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.lope_status_string(code)
@@ -412,7 +442,7 @@ def test_tune_cache_registration(tmp_path):
     from paper_1502_03504_amd import tune
     names = {f["name"]: vid for vid, f in tune._variant_table().items()}
     t1 = [n for n in names if n.startswith("star3d_float_r1_t1_")][0]
-    t2 = [n for n in names if n.startswith("star3d_float_r1_t2_")][0]
+    t2 = [n for n in names if n.startswith("star3df_float_r1_t2_")][0]
     cache = {"gfx950|3|1|f32|star|18|0": {"variant": t2, "tdepth": 2, "chunk": 16, "gpts": 1.0},
              "gfx950|3|1|f32|star|18|1": {"variant": t1, "tdepth": 1, "chunk": 8, "gpts": 1.0},
              "gfx950|3|1|f32|star|18|3": {"variant": "no_such_variant", "tdepth": 3, "chunk": 8, "gpts": 1.0}}
