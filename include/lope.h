@@ -379,6 +379,35 @@ int lope_batch_result_index(const lope_batch_plan* plan, int32_t* out);
  * may still be running).  NULL is a no-op. */
 int lope_batch_plan_destroy(lope_batch_plan* plan);
 
+/* Bytes of the library's static device scratch used by lope_batch_apply_noalloc
+ * (4 MiB: the descriptors of up to about 21,000 grids, or some 200,000 strips
+ * of 16 bytes). */
+#define LOPE_BATCH_SCRATCH_BYTES (4u << 20)
+
+/* For callers that cannot allocate device memory (serving loops that must not
+ * call hipMalloc, harnesses that forbid it): the work of
+ * lope_batch_plan_create + lope_batch_apply + lope_batch_plan_destroy in one
+ * call that allocates nothing.  The grid descriptors and strip tables go into
+ * a fixed device array of LOPE_BATCH_SCRATCH_BYTES that the library holds on
+ * each device it runs on until the process ends; a batch whose tables do not
+ * fit returns LOPE_ERR_UNSUPPORTED (naming the bytes needed) before anything
+ * is enqueued, as do more than LOPE_BATCH_SCRATCH_BYTES / (descriptor size)
+ * grids.
+ *   items, n_items, n_steps: as for lope_batch_plan_create (same checks).
+ *   tdepth: sweeps per launch 1..8, or 0 for the tiling registered with
+ *           lope_batch_tune_set (as a new plan takes); rows: 1..65536, or 0
+ *           likewise.  The result equals lope_batch_apply's value for value.
+ *   result_index: set to 0 if every grid's state ends in its src, 1 if in its
+ *           dst; must not be NULL.
+ * The tables are written into the array from host memory on `stream` and the
+ * call waits for that copy (so for the work already on `stream`); the sweeps
+ * themselves are enqueued and run asynchronously.  A capturing stream gives
+ * LOPE_ERR_UNSUPPORTED.  Every call on a device reuses that device's one
+ * array: calls that overlap on one device (other streams or threads while
+ * sweeps of an earlier call still run) race and give wrong results. */
+int lope_batch_apply_noalloc(const lope_batch_item* items, int64_t n_items, int64_t n_steps, int32_t tdepth,
+                             int32_t rows, void* stream, int32_t* result_index);
+
 /* ---- measurement aid ---------------------------------------------------------- */
 
 /* Copies `bytes` bytes from src to dst (device pointers, 16-byte aligned,

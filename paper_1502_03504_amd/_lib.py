@@ -122,6 +122,8 @@ SIGNATURES = {
     "lope_batch_tune_set": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
     "lope_batch_result_index": (ctypes.c_int, [c_void_p, P(ctypes.c_int32)]),
     "lope_batch_plan_destroy": (ctypes.c_int, [c_void_p]),
+    "lope_batch_apply_noalloc": (ctypes.c_int, [P(lope_batch_item), ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                                ctypes.c_int32, c_void_p, P(ctypes.c_int32)]),
     "lope_copy_stream": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p]),
     "lope_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lope_last_error": (ctypes.c_char_p, []),

@@ -79,6 +79,31 @@ class BatchPlan:
             pass
 
 
+def _item_array(entries):
+    from . import _Stencil, _bc
+    stencils = [_Stencil(e[2]) for e in entries]
+    arr = (_lib.lope_batch_item * max(1, len(entries)))()
+    for i, (src, dst, _, bc) in enumerate(entries):
+        arr[i].src = src.descriptor()
+        arr[i].dst = dst.descriptor()
+        arr[i].stencil = stencils[i].c
+        arr[i].bc = _bc(bc, 2)
+    return arr, stencils
+
+
+def lope_batch_apply_noalloc(entries, n_steps: int, tdepth: int = 0, rows: int = 0, stream=None) -> int:
+    """Advance every (src, dst, stencil, bc) entry n_steps sweeps without a
+    plan (no device allocation: the tables go to the library's static
+    scratch); returns 0 if the states end in the src grids, 1 if in dst."""
+    from . import _stream
+    entries = list(entries)
+    arr, stencils = _item_array(entries)
+    idx = ctypes.c_int32(-1)
+    check(load().lope_batch_apply_noalloc(arr, len(entries), int(n_steps), int(tdepth), int(rows), _stream(stream),
+                                          ctypes.byref(idx)))
+    return idx.value
+
+
 def lope_batch_plan_create(entries, n_steps: int, stream=None) -> BatchPlan:
     return BatchPlan(entries, n_steps, stream)
 

@@ -830,6 +830,47 @@ hipError_t record_batch_graph(const lope_batch_plan* p, hipGraphExec_t* out) {
 
 }  // namespace
 
+// ---- batches without device allocation ----
+// The grid descriptors and strip tables of lope_batch_apply_noalloc live in
+// this fixed array (one copy per device, kept until the process ends).  Host
+// code never passes the symbol itself to a kernel or copy: it uses the device
+// address hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) unsigned char scratch[LOPE_BATCH_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoallocMaxDevices = 64;
+constexpr int64_t kNoallocMaxGrids = LOPE_BATCH_SCRATCH_BYTES / sizeof(BatchGrid);
+std::mutex g_noalloc_mu;                             // one call at a time builds and uploads tables
+void* g_scratch_dev[kNoallocMaxDevices] = {};        // device address of `scratch` per device
+// host staging and working storage (static: the call allocates nothing)
+alignas(256) unsigned char g_noalloc_stage[LOPE_BATCH_SCRATCH_BYTES];
+int64_t g_noalloc_order[kNoallocMaxGrids], g_noalloc_sorted[kNoallocMaxGrids];
+BatchSpan g_noalloc_spans[2 * kNoallocMaxGrids];
+int8_t g_noalloc_range[kNoallocMaxGrids];
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.  Caller holds g_noalloc_mu.
+int noalloc_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    if (dev < 0 || dev >= kNoallocMaxDevices) return fail(LOPE_ERR_UNSUPPORTED, "device %d out of range", dev);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "address of the static batch scratch");
+        if (!p) return fail(LOPE_ERR_HIP, "address of the static batch scratch: null");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return LOPE_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
 extern "C" {
 
 int lope_get_device(int ordinal, int* out) {
@@ -1371,6 +1412,71 @@ int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream) {
 
 int lope_batch_plan_destroy(lope_batch_plan* plan) {
     plan_free(plan);
+    return LOPE_OK;
+}
+
+int lope_batch_apply_noalloc(const lope_batch_item* items, int64_t n_items, int64_t n_steps, int32_t tdepth,
+                             int32_t rows, void* stream, int32_t* result_index) {
+    if (!result_index) return fail(LOPE_ERR_INVALID_ARG, "null result_index");
+    *result_index = 0;
+    if (tdepth < 0 || tdepth > kBatchMaxDepth)
+        return fail(LOPE_ERR_INVALID_ARG, "tdepth %d not in 0..%d", tdepth, kBatchMaxDepth);
+    if (rows < 0 || rows > kBatchMaxRows) return fail(LOPE_ERR_INVALID_ARG, "rows %d not in 0..%d", rows, kBatchMaxRows);
+    if (n_items > kNoallocMaxGrids)
+        return fail(LOPE_ERR_UNSUPPORTED, "%lld grids: the static scratch holds the descriptors of at most %lld",
+                    (long long)n_items, (long long)kNoallocMaxGrids);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    int rc, dtype = LOPE_F32;
+    if ((rc = batch_check(items, n_items, n_steps, &dtype, g_noalloc_spans))) return rc;
+    const hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return hip_fail(e, "stream capture query");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(LOPE_ERR_UNSUPPORTED, "lope_batch_apply_noalloc uploads its tables and waits; it cannot be captured");
+    int64_t points = 0;
+    for (int64_t i = 0; i < n_items; ++i) points += items[i].src.n[0] * items[i].src.n[1];
+    int depth = 0, nrows = 0;
+    batch_tiling(dtype, points, &depth, &nrows);
+    if (tdepth > 0) depth = tdepth;
+    if (rows > 0) nrows = rows;
+    const int64_t passes = n_steps / depth + (n_steps % depth ? 1 : 0);
+    if (n_items == 0 || passes == 0) return LOPE_OK;
+    const int rem = (int)(n_steps % depth);
+    void* dev = nullptr;
+    if ((rc = noalloc_scratch(&dev))) return rc;
+    batch_order(items, n_items, g_noalloc_order, g_noalloc_sorted, g_noalloc_range);
+    const int64_t nfull = batch_strips(items, g_noalloc_order, n_items, depth, nrows, nullptr, 0);
+    const int64_t nrem = rem ? batch_strips(items, g_noalloc_order, n_items, rem, nrows, nullptr, 0) : 0;
+    const size_t gbytes = round256((size_t)n_items * sizeof(BatchGrid));
+    const size_t fbytes = round256((size_t)nfull * sizeof(BatchItem));
+    const size_t need = gbytes + fbytes + (size_t)nrem * sizeof(BatchItem);
+    if (need > (size_t)LOPE_BATCH_SCRATCH_BYTES)
+        return fail(LOPE_ERR_UNSUPPORTED,
+                    "the batch's tables need %zu bytes (%lld grids, %lld + %lld strips); the static scratch holds %zu",
+                    need, (long long)n_items, (long long)nfull, (long long)nrem, (size_t)LOPE_BATCH_SCRATCH_BYTES);
+    // the tables, laid out as on the device: descriptors, full-pass strips, remainder strips
+    BatchGrid* hg = reinterpret_cast<BatchGrid*>(g_noalloc_stage);
+    BatchItem* hfull = reinterpret_cast<BatchItem*>(g_noalloc_stage + gbytes);
+    BatchItem* hrem = reinterpret_cast<BatchItem*>(g_noalloc_stage + gbytes + fbytes);
+    {
+        static thread_local SweepJob job;
+        for (int64_t i = 0; i < n_items; ++i)
+            batch_grid_desc(&items[i].src, &items[i].dst, &items[i].stencil, &items[i].bc, job, hg[i]);
+    }
+    batch_strips(items, g_noalloc_order, n_items, depth, nrows, hfull, nfull);
+    if (rem) batch_strips(items, g_noalloc_order, n_items, rem, nrows, hrem, nrem);
+    // ordered after earlier work on `stream`; the wait frees the staging
+    // memory for the next call
+    unsigned char* d = static_cast<unsigned char*>(dev);
+    if ((e = hipMemcpyAsync(d, g_noalloc_stage, need, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "batch table upload to the static scratch");
+    e = enqueue_passes(reinterpret_cast<const BatchGrid*>(d), reinterpret_cast<const BatchItem*>(d + gbytes), (int)nfull,
+                       rem ? reinterpret_cast<const BatchItem*>(d + gbytes + fbytes) : nullptr, (int)nrem, n_steps,
+                       depth, dtype, s);
+    if (e != hipSuccess) return hip_fail(e, "batch pass launch");
+    *result_index = (int32_t)(passes & 1);
     return LOPE_OK;
 }
 

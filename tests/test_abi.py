@@ -220,7 +220,7 @@ def test_batch_validation():
 def test_batch_buffers_shared_across_items_rejected():
     """Every pass writes one buffer of every item while reading the other, so
     a buffer overlapping another item's buffer is an alias (checked on the
-    host before the device is touched)."""
+    host before the device is touched), for plans and the no-alloc call."""
     s2, _k = stencil(ndim=2, r=1)
     it = (_lib.lope_batch_item * 3)()
     base = [0x100000, 0x200000, 0x300000, 0x400000, 0x500000, 0x600000]
@@ -230,13 +230,35 @@ def test_batch_buffers_shared_across_items_rejected():
         it[i].stencil = s2
         it[i].bc = bc()
     out = ctypes.c_void_p()
+    idx = ctypes.c_int32()
     assert L.lope_batch_plan_create(it, 3, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_NO_DEVICE
+    assert L.lope_batch_apply_noalloc(it, 3, 10, 0, 0, None, ctypes.byref(idx)) == _lib.LOPE_ERR_NO_DEVICE
     it[2].dst = grid(ndim=2, origin=base[0] + 4 * 20)      # inside item 0's src interior
     assert L.lope_batch_plan_create(it, 3, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_ALIAS
     assert b"items[0].src" in L.lope_last_error() and b"items[2].dst" in L.lope_last_error()
+    assert L.lope_batch_apply_noalloc(it, 3, 10, 0, 0, None, ctypes.byref(idx)) == _lib.LOPE_ERR_ALIAS
     it[2].dst = grid(ndim=2, origin=base[5])
     it[1].src = grid(ndim=2, origin=base[4])               # the same buffer as item 2's src
     assert L.lope_batch_plan_create(it, 3, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_ALIAS
+
+
+def test_batch_noalloc_validation():
+    s2, _k = stencil(ndim=2, r=1)
+    it = (_lib.lope_batch_item * 1)()
+    it[0].src = grid(ndim=2)
+    it[0].dst = grid(ndim=2, origin=far())
+    it[0].stencil = s2
+    it[0].bc = bc()
+    idx = ctypes.c_int32(5)
+    assert L.lope_batch_apply_noalloc(it, 1, 4, 0, 0, None, None) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_apply_noalloc(it, 1, 4, 9, 0, None, ctypes.byref(idx)) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_apply_noalloc(it, 1, 4, 0, -1, None, ctypes.byref(idx)) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_apply_noalloc(it, 1, 4, 0, 1 << 17, None, ctypes.byref(idx)) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_apply_noalloc(it, -1, 4, 0, 0, None, ctypes.byref(idx)) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_apply_noalloc(it, 1, 4, 0, 0, None, ctypes.byref(idx)) == _lib.LOPE_ERR_NO_DEVICE
+    assert idx.value == 0
+    many = 1 + (4 << 20) // 192                            # more descriptors than the scratch holds
+    assert L.lope_batch_apply_noalloc(None, many, 4, 0, 0, None, ctypes.byref(idx)) == _lib.LOPE_ERR_UNSUPPORTED
 
 
 def test_copy_stream_validation():
