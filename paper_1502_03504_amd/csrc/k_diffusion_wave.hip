@@ -40,22 +40,30 @@ __device__ __forceinline__ Rsrc plane_rsrc(const void* base, int64_t bytes) {
 }
 
 // Raw-bit loads and stores through a plane's buffer resource.
-template <typename T>
-__device__ __forceinline__ T bload(Rsrc r, unsigned voff, int soff);
-template <>
-__device__ __forceinline__ float bload<float>(Rsrc r, unsigned voff, int soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+// AUX: the cache-policy bits of the access (0: default; 2: streaming).
+template <typename T, int AUX = 0>
+__device__ __forceinline__ T bload(Rsrc r, unsigned voff, int soff) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, AUX));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, AUX));
 }
-template <>
-__device__ __forceinline__ double bload<double>(Rsrc r, unsigned voff, int soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
-}
+template <int AUX = 0>
 __device__ __forceinline__ void bstore(float v, Rsrc r, unsigned voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, soff, AUX);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bstore(double v, Rsrc r, unsigned voff, int soff) {
     typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) B64;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, v), r, (int)voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, v), r, (int)voff, soff, AUX);
+}
+// f(integral_constant<S>) ... f(integral_constant<E-1>), unrolled at compile time
+template <int S, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (S < E) {
+        f(std::integral_constant<int, S>{});
+        static_for<S + 1, E>(f);
+    }
 }
 
 // DPP lane shifts over the whole wave (bound_ctrl off: a lane whose source
@@ -126,11 +134,12 @@ struct Cols {
         for (int r = 0; r < NR; ++r) row[r] = (int)((unsigned)wrap_index(b.y0 - 1 + r, g.ny) * (unsigned)g.sy * (unsigned)sizeof(T));
     }
     // rows 0 .. NR-1 of plane q (wrapped) into v, the outside columns into e
+    template <int AUX = 0>
     __device__ __forceinline__ void load(int q, int nz, T (&v)[NR], T& e) const {
         const Rsrc rs = plane_rsrc(base + (int64_t)wrap_index(q, nz) * pbytes, pbytes);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = bload<T>(rs, xo, row[r]);
-        e = bload<T>(rs, eo, 0);
+        for (int r = 0; r < NR; ++r) v[r] = bload<T, AUX>(rs, xo, row[r]);
+        e = bload<T, AUX>(rs, eo, 0);
     }
 };
 
@@ -141,10 +150,12 @@ __device__ __forceinline__ void x_neighbours(const T (&v)[NR], T e, int r, T& le
     right = lane_shift<kWaveShl1>(v[r], lane_value(e, 32 + r - 1));
 }
 
-template <typename T, int P, int NW>
+// PF: planes loaded ahead of the one being computed (1 or 2); LA / SA: cache
+// policy of the loads / stores.
+template <typename T, int P, int NW, int PF = 1, int LA = 0, int SA = 0>
 __global__ void __launch_bounds__(NW * 64)
 k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strips, int segs, int nwaves, int nbp) {
-    constexpr int NR = P + 2;
+    constexpr int NR = P + 2, NB = PF + 1;
     Brick b;
     if (!brick_of(src, P, chunk, strips, segs, nwaves, nbp, NW, b)) return;
     Cols<T, NR> cu, ck;
@@ -157,17 +168,23 @@ k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strip
     const unsigned so = (unsigned)(b.x0 + lane) * (unsigned)sizeof(T);
     const T half = (T)0.5;
 
-    T u[2][NR], k[2][NR], eu[2], ek[2];   // current plane and the one in flight
-    T pu[P], pk[P], acc[P];               // plane j-1: centre values and its partial sums
+    T u[NB][NR], k[NB][NR], eu[NB], ek[NB];   // the current plane and PF planes in flight
+    T pu[P], pk[P], acc[P];                   // plane j-1: centre values and its partial sums
     const int jstart = b.z0 - 1, jend = b.zend;
-    cu.load(jstart, nz, u[0], eu[0]);
-    ck.load(jstart, nz, k[0], ek[0]);
+    static_for<0, PF>([&](auto q) __attribute__((always_inline)) {
+        constexpr int Q = decltype(q)::value;
+        if (jstart + Q <= jend) {
+            cu.template load<LA>(jstart + Q, nz, u[Q], eu[Q]);
+            ck.template load<LA>(jstart + Q, nz, k[Q], ek[Q]);
+        }
+    });
 
+    // march step j with plane j in buffer C
     auto step = [&](int j, auto cur_c) __attribute__((always_inline)) {
-        constexpr int C = decltype(cur_c)::value, N = C ^ 1;
-        if (j + 1 <= jend) {
-            cu.load(j + 1, nz, u[N], eu[N]);
-            ck.load(j + 1, nz, k[N], ek[N]);
+        constexpr int C = decltype(cur_c)::value, N = (C + PF) % NB;
+        if (j + PF <= jend) {
+            cu.template load<LA>(j + PF, nz, u[N], eu[N]);
+            ck.template load<LA>(j + PF, nz, k[N], ek[N]);
         }
         const T(&U)[NR] = u[C];
         const T(&K)[NR] = k[C];
@@ -199,7 +216,8 @@ k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strip
                 const T d = U[r + 1] - pu[r];
                 const int y = b.y0 + r;
                 if (done && y < ny && xin)
-                    bstore(fma(dt, fma(w, d, acc[r]), pu[r]), rd, so, (int)((unsigned)y * (unsigned)dst.sy * (unsigned)sizeof(T)));
+                    bstore<SA>(fma(dt, fma(w, d, acc[r]), pu[r]), rd, so,
+                               (int)((unsigned)y * (unsigned)dst.sy * (unsigned)sizeof(T)));
                 if (own) a[r] = fma(w, -d, a[r]);
             }
         }
@@ -211,18 +229,18 @@ k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strip
         }
     };
     int j = jstart;
-    for (; j + 1 <= jend; j += 2) {
-        step(j, std::integral_constant<int, 0>{});
-        step(j + 1, std::integral_constant<int, 1>{});
-    }
-    if (j <= jend) step(j, std::integral_constant<int, 0>{});
+    for (; j + NB - 1 <= jend; j += NB)
+        static_for<0, NB>([&](auto c) __attribute__((always_inline)) { step(j + decltype(c)::value, c); });
+    static_for<0, NB - 1>([&](auto c) __attribute__((always_inline)) {
+        if (j + decltype(c)::value <= jend) step(j + decltype(c)::value, c);
+    });
 }
 
-template <typename T, typename TG, int P, int NW>
+template <typename T, typename TG, int P, int NW, int PF = 1, int SA = 0>
 __global__ void __launch_bounds__(NW * 64)
 k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, T dt, int chunk, int strips, int segs,
                int nwaves, int nbp) {
-    constexpr int NR = P + 2;
+    constexpr int NR = P + 2, NB = PF + 1;
     Brick b;
     if (!brick_of(lnext, P, chunk, strips, segs, nwaves, nbp, NW, b)) return;
     Cols<T, NR> cl, cu, ck;
@@ -237,22 +255,27 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
     const int64_t lpb = lam.sz * (int64_t)sizeof(T), gpb = gk.sz * (int64_t)sizeof(TG);
     const T half = (T)0.5, hdt = (T)0.5 * dt;
 
-    T l[2][NR], u[2][NR], k[2][NR], el[2], eu[2], ek[2];
+    T l[NB][NR], u[NB][NR], k[NB][NR], el[NB], eu[NB], ek[NB];
     T pl[P], pu[P], pk[P], al[P], ag[P];
     TG gold[P];   // kappa gradient of plane j-1, read one step ahead
     const int jstart = b.z0 - 1, jend = b.zend;
-    cl.load(jstart, nz, l[0], el[0]);
-    cu.load(jstart, nz, u[0], eu[0]);
-    ck.load(jstart, nz, k[0], ek[0]);
+    static_for<0, PF>([&](auto q) __attribute__((always_inline)) {
+        constexpr int Q = decltype(q)::value;
+        if (jstart + Q <= jend) {
+            cl.load(jstart + Q, nz, l[Q], el[Q]);
+            cu.load(jstart + Q, nz, u[Q], eu[Q]);
+            ck.load(jstart + Q, nz, k[Q], ek[Q]);
+        }
+    });
 #pragma unroll
     for (int r = 0; r < P; ++r) gold[r] = (TG)0;
 
     auto step = [&](int j, auto cur_c) __attribute__((always_inline)) {
-        constexpr int C = decltype(cur_c)::value, N = C ^ 1;
-        if (j + 1 <= jend) {
-            cl.load(j + 1, nz, l[N], el[N]);
-            cu.load(j + 1, nz, u[N], eu[N]);
-            ck.load(j + 1, nz, k[N], ek[N]);
+        constexpr int C = decltype(cur_c)::value, N = (C + PF) % NB;
+        if (j + PF <= jend) {
+            cl.load(j + PF, nz, l[N], el[N]);
+            cu.load(j + PF, nz, u[N], eu[N]);
+            ck.load(j + PF, nz, k[N], ek[N]);
         }
         const T(&L)[NR] = l[C];
         const T(&U)[NR] = u[C];
@@ -299,9 +322,10 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
                 const T du = U[r + 1] - pu[r];   // u_j - u_{j-1}
                 const int y = b.y0 + r;
                 if (done && y < ny && xin) {
-                    bstore(fma(dt, fma(w, dl, al[r]), pl[r]), rl, so, (int)((unsigned)y * (unsigned)lam.sy * (unsigned)sizeof(T)));
-                    bstore(gold[r] + (TG)(hdt * fma(du, -dl, ag[r])), rg, sg,
-                           (int)((unsigned)y * (unsigned)gk.sy * (unsigned)sizeof(TG)));
+                    bstore<SA>(fma(dt, fma(w, dl, al[r]), pl[r]), rl, so,
+                               (int)((unsigned)y * (unsigned)lam.sy * (unsigned)sizeof(T)));
+                    bstore<SA>(gold[r] + (TG)(hdt * fma(du, -dl, ag[r])), rg, sg,
+                               (int)((unsigned)y * (unsigned)gk.sy * (unsigned)sizeof(TG)));
                 }
                 if (own) {
                     a[r] = fma(w, -dl, a[r]);
@@ -320,11 +344,11 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
         }
     };
     int j = jstart;
-    for (; j + 1 <= jend; j += 2) {
-        step(j, std::integral_constant<int, 0>{});
-        step(j + 1, std::integral_constant<int, 1>{});
-    }
-    if (j <= jend) step(j, std::integral_constant<int, 0>{});
+    for (; j + NB - 1 <= jend; j += NB)
+        static_for<0, NB>([&](auto c) __attribute__((always_inline)) { step(j + decltype(c)::value, c); });
+    static_for<0, NB - 1>([&](auto c) __attribute__((always_inline)) {
+        if (j + decltype(c)::value <= jend) step(j + decltype(c)::value, c);
+    });
 }
 
 // Bricks of 64 columns by P rows; the z-chunk balanced against the waves the
@@ -346,12 +370,16 @@ bool wave_geometry(K kernel, int nw_per_block, int P, const DevGrid& g, int& chu
     return true;
 }
 
+// Measured on MI355X (float32, 256^3 and 512^3): streaming stores, loads with
+// the default policy, one plane in flight; 4-row bricks for the reverse step
+// and for forward steps up to 2^25 points (their planes fit the last-level
+// cache), 8-row bricks for larger forward steps (fewer re-read halo rows).
 constexpr int kVarNW = 4;
-constexpr int kFwdP32 = 8, kFwdP64 = 4, kAdjP32 = 6, kAdjP64 = 4;
+constexpr int kStream = 2;   // cache-policy bits of a streaming store
 
 template <typename T, int P>
 hipError_t fwd(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, double dt, hipStream_t s) {
-    constexpr auto kernel = k_varw_forward<T, P, kVarNW>;
+    constexpr auto kernel = k_varw_forward<T, P, kVarNW, 1, 0, kStream>;
     int chunk, strips, segs, nw, nbp;
     if (!wave_geometry(kernel, kVarNW, P, src, chunk, strips, segs, nw, nbp)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(kernel, dim3(nbp), dim3(kVarNW * 64), 0, s, src, dst, kappa, (T)dt, chunk, strips, segs, nw, nbp);
@@ -361,7 +389,7 @@ hipError_t fwd(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, dou
 template <typename T, typename TG, int P>
 hipError_t adj(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, const DevGrid& kappa, const DevGrid& gk,
                double dt, hipStream_t s) {
-    constexpr auto kernel = k_varw_adjoint<T, TG, P, kVarNW>;
+    constexpr auto kernel = k_varw_adjoint<T, TG, P, kVarNW, 1, kStream>;
     int chunk, strips, segs, nw, nbp;
     if (!wave_geometry(kernel, kVarNW, P, lam_next, chunk, strips, segs, nw, nbp)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(kernel, dim3(nbp), dim3(kVarNW * 64), 0, s, lam_next, lam, u, kappa, gk, (T)dt, chunk, strips,
@@ -375,16 +403,17 @@ bool var_wave_fits(const DevGrid& g, int esize) { return g.sz * (int64_t)esize <
 
 hipError_t launch_var_forward_wave(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, int dtype, double dt,
                                    hipStream_t s) {
-    if (dtype == LOPE_F32) return fwd<float, kFwdP32>(src, dst, kappa, dt, s);
-    return fwd<double, kFwdP64>(src, dst, kappa, dt, s);
+    if (dtype == LOPE_F64) return fwd<double, 4>(src, dst, kappa, dt, s);
+    if ((int64_t)src.nx * src.ny * src.nz <= ((int64_t)1 << 25)) return fwd<float, 4>(src, dst, kappa, dt, s);
+    return fwd<float, 8>(src, dst, kappa, dt, s);
 }
 
 hipError_t launch_var_adjoint_wave(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, const DevGrid& kappa,
                                    const DevGrid& gk, int dtype, int gk_dtype, double dt, hipStream_t s) {
-    if (dtype == LOPE_F32 && gk_dtype == LOPE_F32) return adj<float, float, kAdjP32>(lam_next, lam, u, kappa, gk, dt, s);
-    if (dtype == LOPE_F32) return adj<float, double, kAdjP32>(lam_next, lam, u, kappa, gk, dt, s);
-    if (gk_dtype == LOPE_F64) return adj<double, double, kAdjP64>(lam_next, lam, u, kappa, gk, dt, s);
-    return adj<double, float, kAdjP64>(lam_next, lam, u, kappa, gk, dt, s);
+    if (dtype == LOPE_F32 && gk_dtype == LOPE_F32) return adj<float, float, 4>(lam_next, lam, u, kappa, gk, dt, s);
+    if (dtype == LOPE_F32) return adj<float, double, 4>(lam_next, lam, u, kappa, gk, dt, s);
+    if (gk_dtype == LOPE_F64) return adj<double, double, 4>(lam_next, lam, u, kappa, gk, dt, s);
+    return adj<double, float, 4>(lam_next, lam, u, kappa, gk, dt, s);
 }
 
 }  // namespace lope
