@@ -141,10 +141,11 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
     plan = L.BatchPlan(entries, steps)
     s = torch.cuda.current_stream()
 
-    def timed(fn):
+    def timed(fn, n=None):
+        fn()
         fn()
         ts = []
-        for _ in range(reps):
+        for _ in range(n or max(reps, 5)):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
             fn()
@@ -158,7 +159,7 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
     # batch's dtype and size (what lope_batch_apply does by default)
     depth, rows = plan.tiles()
     tb = timed(plan.apply)
-    tp = timed(plan.apply_per_grid) if per_grid else None
+    tp = timed(plan.apply_per_grid, reps) if per_grid else None
     # context only: every depth at the plan's rows
     by_depth = {}
     if by_depth_sweep:

@@ -30,6 +30,9 @@
  *     them into the caller's graph; the exceptions are lope_iterate_until,
  *     which waits on the host and refuses a capturing stream, and the batch
  *     plan calls, whose own rules are given with them.
+ *   - Logging: with LOPE_LOG=1 in the environment every compute call writes
+ *     one line to stderr naming the kernel (and depth, chunk or tiling) it
+ *     chose.
  *   - Errors: every call returns LOPE_OK (0) or a negative lope_status.  All
  *     structural validation runs before any HIP call; on error nothing has
  *     been enqueued.  No exception crosses the ABI, nothing calls exit(), and

@@ -193,6 +193,26 @@ int device_ready() {
     return LOPE_OK;
 }
 
+// LOPE_LOG=1 in the environment: one line on stderr per compute call naming
+// the kernel chosen (read once per process).
+bool log_enabled() {
+    static const bool on = [] {
+        const char* v = getenv("LOPE_LOG");
+        return v && v[0] == '1';
+    }();
+    return on;
+}
+
+void log_line(const char* fmt, ...) {
+    if (!log_enabled()) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "lope: %s\n", buf);
+}
+
 // The whole padded box must be device memory inside one allocation, on the
 // current device.
 int check_memory(const lope_grid* g, const char* name) {
@@ -411,6 +431,8 @@ struct Plan {
     int chunk;
 };
 
+const char* variant_name(int variant) { return variant > 0 ? registry().v[variant - 1].name : "generic"; }
+
 // The registered choice for a request of `req` sweeps per pass (0 = automatic)
 // on a job like j: the entry of j's own size bucket if its variant fits j,
 // else the fitting entry of the same class (ndim, radius, dtype, shape, request,
@@ -527,6 +549,9 @@ int iterate_impl(const lope_grid* a, const lope_grid* b, const lope_stencil* st,
     if (variant_req > 0 && !variant_fits(registry().v[variant_req - 1], job, registry().v[variant_req - 1].tdepth))
         return fail(LOPE_ERR_UNSUPPORTED, "variant %d does not fit this grid/stencil", variant_req);
     const Plan plan = choose(job, tdepth, variant_req, chunk_req);
+    log_line("iterate %lld sweeps on %dx%dx%d %s radius %d: %s, %d per pass, chunk %d", (long long)n_steps, job.src.nx,
+             job.src.ny, job.src.nz, job.dtype == LOPE_F64 ? "f64" : "f32", job.radius, variant_name(plan.variant),
+             plan.tdepth, plan.chunk);
     const hipStream_t s = (hipStream_t)stream;
     const DevGrid ga = dev_grid(a), gb = dev_grid(b);
     int64_t done = 0, passes = 0;
@@ -1045,6 +1070,8 @@ int stages_impl(const lope_grid* a, const lope_grid* b, const lope_stages* sg, c
     int chunk2 = 0, chunk1 = 0;
     const int v2 = pick(4, &chunk2);   // two steps per pass
     const int v1 = pick(2, &chunk1);   // one step per pass
+    log_line("two-stage steps (%lld) on %dx%dx%d: two per pass %s, one per pass %s", (long long)n_steps, sj.s1.src.nx,
+             sj.s1.src.ny, sj.s1.src.nz, v2 ? variant_name(v2) : "none", v1 ? variant_name(v1) : "k_stages");
     const DevGrid ga = dev_grid(a), gb = dev_grid(b);
     const hipStream_t s = (hipStream_t)stream;
     int64_t done = 0, passes = 0;
@@ -1121,6 +1148,8 @@ int lope_apply_adjoint(const lope_grid* ybar, const lope_grid* xbar, const lope_
     }
     build_job(job, ybar, xbar, st, bc, true);
     const Plan plan = choose(job, 1, 0, 0);
+    log_line("adjoint on %dx%dx%d: %s%s", job.src.nx, job.src.ny, job.src.nz,
+             variant_name(plan.tdepth == 1 ? plan.variant : 0), gbar_dirichlet ? ", gbar" : "");
     return run_pass(job, plan.tdepth == 1 ? plan.variant : 0, plan.chunk, s);
 }
 
@@ -1145,9 +1174,10 @@ int lope_apply_var(const lope_grid* src, const lope_grid* dst, const lope_varcoe
     if (is_empty(src)) return LOPE_OK;
     const DevGrid gs = dev_grid(src), gd = dev_grid(dst), gk = dev_grid(vc->kappa);
     const int es = (int)elem_size(src->dtype);
-    const hipError_t e = var_wave_fits(gs, es) && var_wave_fits(gd, es) && var_wave_fits(gk, es)
-                             ? launch_var_forward_wave(gs, gd, gk, src->dtype, vc->dt, (hipStream_t)stream)
-                             : launch_var_forward(gs, gd, gk, src->dtype, vc->dt, (hipStream_t)stream);
+    const bool wave = var_wave_fits(gs, es) && var_wave_fits(gd, es) && var_wave_fits(gk, es);
+    log_line("diffusion step on %dx%dx%d: %s", gs.nx, gs.ny, gs.nz, wave ? "k_varw_forward" : "k_var_forward");
+    const hipError_t e = wave ? launch_var_forward_wave(gs, gd, gk, src->dtype, vc->dt, (hipStream_t)stream)
+                              : launch_var_forward(gs, gd, gk, src->dtype, vc->dt, (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion launch");
 }
 
@@ -1185,6 +1215,7 @@ int lope_apply_var_adjoint(const lope_grid* lam_next, const lope_grid* lam, cons
     const int es = (int)elem_size(lam_next->dtype);
     const bool wave = var_wave_fits(gn, es) && var_wave_fits(gl, es) && var_wave_fits(gu, es) &&
                       var_wave_fits(gk, es) && var_wave_fits(gg, (int)elem_size(gkappa->dtype));
+    log_line("diffusion reverse step on %dx%dx%d: %s", gn.nx, gn.ny, gn.nz, wave ? "k_varw_adjoint" : "k_var_adjoint");
     const hipError_t e =
         wave ? launch_var_adjoint_wave(gn, gl, gu, gk, gg, lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream)
              : launch_var_adjoint(gn, gl, gu, gk, gg, lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream);
@@ -1222,6 +1253,8 @@ int lope_apply_var_adjoint2(const lope_grid* lam_next, const lope_grid* lam, con
         if ((rc = check_memory(ins[i], names[i]))) return rc;
     if ((rc = check_memory(lam, "lam")) || (rc = check_memory(gkappa, "gkappa"))) return rc;
     if (is_empty(lam_next)) return LOPE_OK;
+    log_line("diffusion reverse pair on %lldx%lldx%lld: k_var_adjoint2", (long long)lam_next->n[0],
+             (long long)lam_next->n[1], (long long)lam_next->n[2]);
     const hipError_t e = launch_var_adjoint2(dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(u_tm1),
                                              dev_grid(vc->kappa), dev_grid(gkappa), lam_next->dtype, gkappa->dtype,
                                              vc->dt, (hipStream_t)stream);
@@ -1374,6 +1407,9 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream) {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(s, &cap);
     if (e != hipSuccess) return hip_fail(e, "stream capture query");
+    log_line("batch of %zu grids, %lld sweeps: %d per launch, %d-row strips, %lld launches%s", plan->grids.size(),
+             (long long)plan->n_steps, plan->tdepth, plan->rows, (long long)plan_passes(plan),
+             cap != hipStreamCaptureStatusNone ? " (into the caller's graph)" : "");
     if (cap != hipStreamCaptureStatusNone) {
         // the caller is recording a graph: its graph takes the launches
         e = enqueue_batch_passes(plan, s);
@@ -1455,6 +1491,8 @@ int lope_batch_apply_noalloc(const lope_batch_item* items, int64_t n_items, int6
         return fail(LOPE_ERR_UNSUPPORTED,
                     "the batch's tables need %zu bytes (%lld grids, %lld + %lld strips); the static scratch holds %zu",
                     need, (long long)n_items, (long long)nfull, (long long)nrem, (size_t)LOPE_BATCH_SCRATCH_BYTES);
+    log_line("batch without allocation, %lld grids, %lld sweeps: %d per launch, %d-row strips, %lld launches, %zu "
+             "bytes of tables", (long long)n_items, (long long)n_steps, depth, nrows, (long long)passes, need);
     // the tables, laid out as on the device: descriptors, full-pass strips, remainder strips
     BatchGrid* hg = reinterpret_cast<BatchGrid*>(g_noalloc_stage);
     BatchItem* hfull = reinterpret_cast<BatchItem*>(g_noalloc_stage + gbytes);
