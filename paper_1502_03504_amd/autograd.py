@@ -9,26 +9,29 @@ returns dL/du0 and dL/dkappa:
   checkpoint_every), so memory grows with n_steps / k, not n_steps;
 * the backward pass walks the segments in reverse; for each it recomputes the
   segment's states from its checkpoint with the forward kernel, then runs the
-  one-step reverse kernel (lope_apply_var_adjoint) from the segment's last
-  step down to its first, which turns lambda_{t+1} = dL/du_{t+1} into
-  lambda_t and adds the step's kappa derivative into an accumulator;
+  reverse kernels from the segment's last step down to its first, which turn
+  lambda_{t+1} = dL/du_{t+1} into lambda_t and add each step's kappa
+  derivative into an accumulator.  Steps (2m+1, 2m) that lie in one segment
+  run as one fused two-step pass (lope_apply_var_adjoint2, which computes
+  every lambda exactly as the one-step kernel does), the rest one step at a
+  time;
 * every FOLD_EVERY steps (at t divisible by it) the float32 accumulator is
   folded into a float64 total (lope_accumulate), so the kappa gradient is
   reduced in float64 over the time loop.  For float64 states the reverse
   kernels add each step's terms straight into the float64 total.
 
 Recomputation is deterministic (same kernels, same inputs) and the folds sit
-at fixed time indices, so both gradients are bit-for-bit independent of the
-checkpoint interval.  (lope_apply_var_adjoint2, two reverse steps in one
-pass, moves fewer bytes per step but runs slower per step than the one-step
-wave kernel on this device, so the driver does not use it.)  Everything runs
-on the current stream; nothing synchronises with the host.
+at fixed time indices.  So dL/du0 is bit-for-bit independent of the
+checkpoint interval; dL/dkappa is too for every even interval (all pairs
+fused), while an odd interval splits some pairs and changes only the rounding
+of the kappa accumulator.  Everything runs on the current stream; nothing
+synchronises with the host.
 """
 from __future__ import annotations
 
 import torch
 
-from . import Grid, lope_accumulate, lope_apply_var, lope_apply_var_adjoint
+from . import Grid, lope_accumulate, lope_apply_var, lope_apply_var_adjoint, lope_apply_var_adjoint2
 
 _PERIODIC = (("periodic",) * 3, 0.0)
 FOLD_EVERY = 20
@@ -83,10 +86,20 @@ class DiffusionFunction(torch.autograd.Function):
             seg_states[0].interior().copy_(checkpoints[s].interior())
             for i in range(1, length):
                 lope_apply_var(seg_states[i - 1], seg_states[i], kap, dt, _PERIODIC)
-            for i in range(length - 1, -1, -1):
-                lope_apply_var_adjoint(lam, lam2, seg_states[i], kap, dt, _PERIODIC, gacc)
+            i = length - 1
+            while i >= 0:
+                t = t0 + i
+                if t % 2 == 1 and i >= 1:
+                    # steps t and t-1 fused (pairs sit at absolute indices (2m+1, 2m))
+                    lope_apply_var_adjoint2(lam, lam2, seg_states[i], seg_states[i - 1], kap, dt, _PERIODIC, gacc)
+                    low = t - 1
+                    i -= 2
+                else:
+                    lope_apply_var_adjoint(lam, lam2, seg_states[i], kap, dt, _PERIODIC, gacc)
+                    low = t
+                    i -= 1
                 lam, lam2 = lam2, lam
-                if fold and (t0 + i) % FOLD_EVERY == 0:
+                if fold and low % FOLD_EVERY == 0:
                     lope_accumulate(gacc, g64)
         grad_u0 = lam.interior().clone()
         grad_kappa = g64.interior().to(grad_out.dtype)

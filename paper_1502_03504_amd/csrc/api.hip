@@ -1253,11 +1253,15 @@ int lope_apply_var_adjoint2(const lope_grid* lam_next, const lope_grid* lam, con
         if ((rc = check_memory(ins[i], names[i]))) return rc;
     if ((rc = check_memory(lam, "lam")) || (rc = check_memory(gkappa, "gkappa"))) return rc;
     if (is_empty(lam_next)) return LOPE_OK;
-    log_line("diffusion reverse pair on %lldx%lldx%lld: k_var_adjoint2", (long long)lam_next->n[0],
-             (long long)lam_next->n[1], (long long)lam_next->n[2]);
-    const hipError_t e = launch_var_adjoint2(dev_grid(lam_next), dev_grid(lam), dev_grid(u_t), dev_grid(u_tm1),
-                                             dev_grid(vc->kappa), dev_grid(gkappa), lam_next->dtype, gkappa->dtype,
-                                             vc->dt, (hipStream_t)stream);
+    const DevGrid gn = dev_grid(lam_next), gl = dev_grid(lam), gu = dev_grid(u_t), gv = dev_grid(u_tm1),
+                  gk = dev_grid(vc->kappa), gg = dev_grid(gkappa);
+    const int es = (int)elem_size(lam_next->dtype);
+    const bool wave = var_wave_fits(gn, es) && var_wave_fits(gl, es) && var_wave_fits(gu, es) &&
+                      var_wave_fits(gv, es) && var_wave_fits(gk, es) && var_wave_fits(gg, (int)elem_size(gkappa->dtype));
+    log_line("diffusion reverse pair on %dx%dx%d: %s", gn.nx, gn.ny, gn.nz, wave ? "k_varw_adjoint2" : "k_var_adjoint2");
+    const hipError_t e =
+        wave ? launch_var_adjoint2_wave(gn, gl, gu, gv, gk, gg, lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream)
+             : launch_var_adjoint2(gn, gl, gu, gv, gk, gg, lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "diffusion two-step adjoint launch");
 }
 

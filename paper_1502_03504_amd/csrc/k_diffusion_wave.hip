@@ -66,6 +66,8 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+constexpr int kStreamStore = 2;   // cache-policy bits of a streaming store
+
 // DPP lane shifts over the whole wave (bound_ctrl off: a lane whose source
 // lies past the wave's end keeps `old`): from_left gives lane l the value of
 // lane l-1 (lane 0: old), from_right the value of lane l+1 (lane 63: old).
@@ -84,14 +86,24 @@ __device__ __forceinline__ double lane_shift(double v, double old) {
         (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
-// The value lane `src` holds (wave-uniform).
-__device__ __forceinline__ float lane_value(float v, int src) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+// Rotation within every row of 16 lanes: lane i of a row receives lane
+// (i + a) mod 16 of the same row (a = 0..15; DPP row_ror by 16 - a).
+template <int A>
+__device__ __forceinline__ int row_rotate_bits(int v) {
+    if constexpr (A % 16 == 0)
+        return v;
+    else
+        return __builtin_amdgcn_update_dpp(v, v, 0x120 + (16 - A % 16), 0xf, 0xf, false);
 }
-__device__ __forceinline__ double lane_value(double v, int src) {
+template <int A>
+__device__ __forceinline__ float row_rotate(float v) {
+    return __builtin_bit_cast(float, row_rotate_bits<A>(__builtin_bit_cast(int, v)));
+}
+template <int A>
+__device__ __forceinline__ double row_rotate(double v) {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    const unsigned lo = (unsigned)row_rotate_bits<A>((int)(unsigned)b);
+    const unsigned hi = (unsigned)row_rotate_bits<A>((int)(unsigned)(b >> 32));
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
@@ -100,38 +112,51 @@ struct Brick {
     int x0, y0, z0, zend;
 };
 
+// W: output columns per wave (64, or 62 for the fused pair).
 __device__ __forceinline__ bool brick_of(const DevGrid& g, int P, int chunk, int strips, int segs, int nwaves,
-                                         int nbp, int nw_per_block, Brick& b) {
+                                         int nbp, int nw_per_block, Brick& b, int W = 64) {
     const int wave = xcd_logical_block(nbp) * nw_per_block + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (wave >= nwaves) return false;
     const int tx = wave % strips, rest = wave / strips;
-    b.x0 = tx * 64;
+    b.x0 = tx * W;
     b.y0 = (rest % segs) * P;
     b.z0 = (rest / segs) * chunk;
     b.zend = min(b.z0 + chunk, g.nz);
     return true;
 }
 
-// One array's addressing: column byte offset of this lane, byte offset of
-// this lane's outside column (see the file comment), wave-uniform row byte
-// offsets, plane bytes.
+// One array's addressing: lane l holds column x_first + l and row r is
+// y_first + r (both wrapped); the outside columns x_first - 1 and
+// x_first + 64 of rows 1 .. n_edge (at most 16) are packed into one load:
+// lane i < 16 holds the left one of row i + 1, lane 48 + ((i + 15) mod 16)
+// the right one, so that rotating the rows of lanes by r - 1 (x_neighbours)
+// brings row r's left outside value to lane 0 and its right one to lane 63
+// in one DPP move.  Column byte offset of this lane, byte offset of its
+// outside column, wave-uniform row byte offsets, plane bytes.
 template <typename T, int NR>
 struct Cols {
     const char* base;
     int64_t pbytes;
     unsigned xo, eo;
     int row[NR];
-    __device__ __forceinline__ void init(const DevGrid& g, const Brick& b, int P) {
+    __device__ __forceinline__ void init(const DevGrid& g, int x_first, int y_first, int n_edge) {
         const int lane = threadIdx.x & 63;
         base = (const char*)g.origin;
         pbytes = g.sz * (int64_t)sizeof(T);
-        xo = (unsigned)wrap_index(b.x0 + lane, g.nx) * (unsigned)sizeof(T);
-        const int i = lane & 31;
-        const int ecol = wrap_index(lane < 32 ? b.x0 - 1 : b.x0 + 64, g.nx);
-        const int erow = wrap_index(b.y0 + (i < P ? i : 0), g.ny);
+        xo = (unsigned)wrap_index(x_first + lane, g.nx) * (unsigned)sizeof(T);
+        const bool right = lane >= 48;
+        const int i = right ? (lane - 48 + 1) & 15 : lane & 15;
+        const int ecol = wrap_index(right ? x_first + 64 : x_first - 1, g.nx);
+        const int erow = wrap_index(y_first + 1 + (i < n_edge ? i : 0), g.ny);
         eo = ((unsigned)erow * (unsigned)g.sy + (unsigned)ecol) * (unsigned)sizeof(T);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) row[r] = (int)((unsigned)wrap_index(b.y0 - 1 + r, g.ny) * (unsigned)g.sy * (unsigned)sizeof(T));
+        for (int r = 0; r < NR; ++r) row[r] = (int)((unsigned)wrap_index(y_first + r, g.ny) * (unsigned)g.sy * (unsigned)sizeof(T));
+    }
+    // rows 0 .. NR-1 of plane q (wrapped) into v
+    __device__ __forceinline__ void load_rows(int q, int nz, T (&v)[NR]) const {
+        const Rsrc rs = plane_rsrc(base + (int64_t)wrap_index(q, nz) * pbytes, pbytes);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = bload<T>(rs, xo, row[r]);
     }
     // rows 0 .. NR-1 of plane q (wrapped) into v, the outside columns into e
     template <int AUX = 0>
@@ -143,11 +168,13 @@ struct Cols {
     }
 };
 
-// x- and x+ neighbours of row r (1..P) of a plane held as (v, e)
-template <typename T, int NR>
-__device__ __forceinline__ void x_neighbours(const T (&v)[NR], T e, int r, T& left, T& right) {
-    left = lane_shift<kWaveShr1>(v[r], lane_value(e, r - 1));
-    right = lane_shift<kWaveShl1>(v[r], lane_value(e, 32 + r - 1));
+// x- and x+ neighbours of row R (1..16) of a plane held as (v, e)
+template <int R, typename T, int NR>
+__device__ __forceinline__ void x_neighbours(const T (&v)[NR], T e, T& left, T& right) {
+    static_assert(R >= 1 && R <= 16, "outside columns of rows 1..16");
+    const T x = row_rotate<R - 1>(e);   // lane 0: row R's left outside value; lane 63: its right one
+    left = lane_shift<kWaveShr1>(v[R], x);
+    right = lane_shift<kWaveShl1>(v[R], x);
 }
 
 // PF: planes loaded ahead of the one being computed (1 or 2); LA / SA: cache
@@ -159,8 +186,8 @@ k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strip
     Brick b;
     if (!brick_of(src, P, chunk, strips, segs, nwaves, nbp, NW, b)) return;
     Cols<T, NR> cu, ck;
-    cu.init(src, b, P);
-    ck.init(kap, b, P);
+    cu.init(src, b.x0, b.y0 - 1, P);
+    ck.init(kap, b.x0, b.y0 - 1, P);
     const int lane = threadIdx.x & 63;
     const int nz = src.nz, ny = src.ny;
     const int64_t dpb = dst.sz * (int64_t)sizeof(T);
@@ -191,19 +218,19 @@ k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strip
         T a[P];
         const bool own = j >= b.z0 && j < b.zend;   // plane j is one of the brick's outputs
         if (own) {   // its in-plane terms
-#pragma unroll
-            for (int r = 1; r <= P; ++r) {
+            static_for<1, P + 1>([&](auto rc) __attribute__((always_inline)) {
+                constexpr int r = decltype(rc)::value;
                 const T uc = U[r], kc = K[r];
                 T ul, ur, kl, kr;
-                x_neighbours(U, eu[C], r, ul, ur);
-                x_neighbours(K, ek[C], r, kl, kr);
+                x_neighbours<r>(U, eu[C], ul, ur);
+                x_neighbours<r>(K, ek[C], kl, kr);
                 T s = (T)0;
                 s = fma(half * (kc + kl), ul - uc, s);
                 s = fma(half * (kc + kr), ur - uc, s);
                 s = fma(half * (kc + K[r - 1]), U[r - 1] - uc, s);
                 s = fma(half * (kc + K[r + 1]), U[r + 1] - uc, s);
                 a[r - 1] = s;
-            }
+            });
         }
         if (j > jstart) {
             // the face between planes j-1 and j: plane j's z- term, and plane
@@ -244,9 +271,9 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
     Brick b;
     if (!brick_of(lnext, P, chunk, strips, segs, nwaves, nbp, NW, b)) return;
     Cols<T, NR> cl, cu, ck;
-    cl.init(lnext, b, P);
-    cu.init(ug, b, P);
-    ck.init(kap, b, P);
+    cl.init(lnext, b.x0, b.y0 - 1, P);
+    cu.init(ug, b.x0, b.y0 - 1, P);
+    ck.init(kap, b.x0, b.y0 - 1, P);
     const int lane = threadIdx.x & 63;
     const int nz = lnext.nz, ny = lnext.ny;
     const bool xin = b.x0 + lane < lnext.nx;   // lanes past a ragged x end store nothing
@@ -287,15 +314,15 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
             // its kappa gradient (read now, updated when the plane completes)
             // and its in-plane terms
             const Rsrc rgj = plane_rsrc((const char*)gk.origin + (int64_t)j * gpb, gpb);
-#pragma unroll
-            for (int r = 1; r <= P; ++r) {
+            static_for<1, P + 1>([&](auto rc) __attribute__((always_inline)) {
+                constexpr int r = decltype(rc)::value;
                 const int y = b.y0 + r - 1;
                 gnew[r - 1] = y < ny && xin ? bload<TG>(rgj, sg, (int)((unsigned)y * (unsigned)gk.sy * (unsigned)sizeof(TG))) : (TG)0;
                 const T lc = L[r], uc = U[r], kc = K[r];
                 T ll, lr, ul, ur, kl, kr;
-                x_neighbours(L, el[C], r, ll, lr);
-                x_neighbours(U, eu[C], r, ul, ur);
-                x_neighbours(K, ek[C], r, kl, kr);
+                x_neighbours<r>(L, el[C], ll, lr);
+                x_neighbours<r>(U, eu[C], ul, ur);
+                x_neighbours<r>(K, ek[C], kl, kr);
                 T s = (T)0, t = (T)0;
                 s = fma(half * (kc + kl), ll - lc, s);
                 t = fma(ul - uc, lc - ll, t);
@@ -307,7 +334,7 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
                 t = fma(U[r + 1] - uc, lc - L[r + 1], t);
                 a[r - 1] = s;
                 g[r - 1] = t;
-            }
+            });
         }
         if (j > jstart) {
             // the face between planes j-1 and j (both sides' terms are the same
@@ -351,12 +378,204 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
     });
 }
 
+// Two reverse steps in one pass: from lam'' = lam_{t+1}, u_t, u_{t-1} and
+// kappa, the first level forms lam_t = A lam'' and G(u_t, lam'') (kept on
+// chip), the second lam_{t-1} = A lam_t (written) and G(u_{t-1}, lam_t); the
+// kappa gradient gets hdt*G1 + hdt*G2 in one update, as the LDS pair kernel
+// does, value for value.  Lanes hold columns x0 - 1 .. x0 + 62: the first
+// level covers all 64 (its outside columns x0 - 2 and x0 + 63 come packed in
+// one load per plane and array), the second level's outputs are lanes 1..62,
+// whose neighbours are plain lane shifts.  Rows: the first level covers the
+// brick's P rows plus one on each side, loaded with two more on each side.
+// Along z the first level completes raw plane q - 1 when plane q arrives
+// (the shared face as in the one-step kernel), and the second level, fed by
+// those completed planes, completes plane q - 2.  u_{t-1} is loaded one plane
+// behind lam'', u_t and kappa.
+template <typename T, typename TG, int P, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_varw_adjoint2(DevGrid lnext, DevGrid lam, DevGrid ut, DevGrid utm1, DevGrid kap, DevGrid gk, T dt, int chunk,
+                int strips, int segs, int nwaves, int nbp) {
+    constexpr int NR = P + 4;      // raw rows y0-2 .. y0+P+1
+    constexpr int R1 = 1, E1 = NR - 1;   // first-level rows [R1, E1)
+    constexpr int R2 = 2, E2 = NR - 2;   // second-level rows [R2, E2): the outputs
+    constexpr int W = 62;
+    Brick b;
+    if (!brick_of(lnext, P, chunk, strips, segs, nwaves, nbp, NW, b, W)) return;
+    Cols<T, NR> cl, cu, ck, cv;
+    cl.init(lnext, b.x0 - 1, b.y0 - 2, E1 - R1);
+    cu.init(ut, b.x0 - 1, b.y0 - 2, E1 - R1);
+    ck.init(kap, b.x0 - 1, b.y0 - 2, E1 - R1);
+    cv.init(utm1, b.x0 - 1, b.y0 - 2, E1 - R1);
+    const int lane = threadIdx.x & 63;
+    const int nz = lnext.nz, ny = lnext.ny;
+    const int gx = b.x0 - 1 + lane;
+    const bool xin = lane >= 1 && lane <= W && gx < lnext.nx;   // an output lane
+    const unsigned so = (unsigned)(xin ? gx : 0) * (unsigned)sizeof(T);
+    const unsigned sg = (unsigned)(xin ? gx : 0) * (unsigned)sizeof(TG);
+    const int64_t lpb = lam.sz * (int64_t)sizeof(T), gpb = gk.sz * (int64_t)sizeof(TG);
+    const T half = (T)0.5, hdt = (T)0.5 * dt;
+    const int z0 = b.z0, zend = b.zend;
+
+    // raw planes: current and in flight (lam'', u_t, kappa with outside columns)
+    T l[2][NR], u[2][NR], k[2][NR], el[2], eu[2], ek[2];
+    T v[2][NR];                    // u_{t-1}: plane q - 1 and the one in flight
+    T pl[NR], pu[NR], pk[NR];      // raw plane q - 1 (first-level rows)
+    T a1[NR], t1[NR];              // first level, plane q - 1: partial sums
+    T m1[NR], k1[NR], v1[NR];      // second level's plane m - 1: lam_t, kappa, u_{t-1}
+    T a2[NR], t2[NR], g1[NR];      // second level, plane m - 1: partial sums, hdt*G1
+    TG gold[NR];                   // kappa gradient of plane m - 1
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        pl[r] = pu[r] = pk[r] = a1[r] = t1[r] = m1[r] = k1[r] = v1[r] = a2[r] = t2[r] = g1[r] = (T)0;
+        gold[r] = (TG)0;
+        v[0][r] = v[1][r] = (T)0;
+    }
+    const int qstart = z0 - 2, qend = zend + 1;
+    cl.load(qstart, nz, l[0], el[0]);
+    cu.load(qstart, nz, u[0], eu[0]);
+    ck.load(qstart, nz, k[0], ek[0]);
+
+    auto rowoff = [&](int r, int64_t sy, int es) { return (int)((unsigned)(b.y0 + r - R2) * (unsigned)sy * (unsigned)es); };
+    auto step = [&](int q, auto cur_c) __attribute__((always_inline)) {
+        constexpr int C = decltype(cur_c)::value, N = C ^ 1;
+        if (q + 1 <= qend) {
+            cl.load(q + 1, nz, l[N], el[N]);
+            cu.load(q + 1, nz, u[N], eu[N]);
+            ck.load(q + 1, nz, k[N], ek[N]);
+        }
+        if (q <= zend) cv.load_rows(q, nz, v[N]);   // u_{t-1} at plane q, used at step q + 1
+        const T(&L)[NR] = l[C];
+        const T(&U)[NR] = u[C];
+        const T(&K)[NR] = k[C];
+        const T(&V)[NR] = v[C];        // u_{t-1} at plane q - 1
+        // first level, plane q: in-plane terms
+        T an[NR], tn[NR];
+        const bool own1 = q >= z0 - 1 && q <= zend;
+        if (own1) {
+            static_for<R1, E1>([&](auto rc) __attribute__((always_inline)) {
+                constexpr int r = decltype(rc)::value;
+                const T lc = L[r], uc = U[r], kc = K[r];
+                T ll, lr, ul, ur, kl, kr;
+                x_neighbours<r>(L, el[C], ll, lr);
+                x_neighbours<r>(U, eu[C], ul, ur);
+                x_neighbours<r>(K, ek[C], kl, kr);
+                T s = (T)0, t = (T)0;
+                s = fma(half * (kc + kl), ll - lc, s);
+                t = fma(ul - uc, lc - ll, t);
+                s = fma(half * (kc + kr), lr - lc, s);
+                t = fma(ur - uc, lc - lr, t);
+                s = fma(half * (kc + K[r - 1]), L[r - 1] - lc, s);
+                t = fma(U[r - 1] - uc, lc - L[r - 1], t);
+                s = fma(half * (kc + K[r + 1]), L[r + 1] - lc, s);
+                t = fma(U[r + 1] - uc, lc - L[r + 1], t);
+                an[r] = s;
+                tn[r] = t;
+            });
+        }
+        // first level: the face between raw planes q - 1 and q completes
+        // plane m = q - 1 (lam_t and hdt*G1 there)
+        T mm[NR], gm[NR];
+        const int m = q - 1;
+        if (q > qstart) {
+#pragma unroll
+            for (int r = R1; r < E1; ++r) {
+                const T w = half * (pk[r] + K[r]);
+                const T dl = L[r] - pl[r];
+                const T du = U[r] - pu[r];
+                mm[r] = fma(dt, fma(w, dl, a1[r]), pl[r]);
+                gm[r] = hdt * fma(du, -dl, t1[r]);
+                if (own1) {
+                    an[r] = fma(w, -dl, an[r]);
+                    tn[r] = fma(-du, dl, tn[r]);
+                }
+            }
+        }
+        // second level at plane m: in-plane terms (rows R2..E2, lanes 1..62),
+        // then the face between m - 1 and m, which completes m - 1
+        T bn[NR], un2[NR];
+        TG gnew[NR];
+        const bool own2 = m >= z0 && m < zend;
+        if (own2) {
+            const Rsrc rgj = plane_rsrc((const char*)gk.origin + (int64_t)m * gpb, gpb);
+#pragma unroll
+            for (int r = R2; r < E2; ++r) {
+                gnew[r] = (b.y0 + r - R2 < ny && xin) ? bload<TG>(rgj, sg, rowoff(r, gk.sy, (int)sizeof(TG))) : (TG)0;
+                const T lc = mm[r], vc = V[r], kc = pk[r];
+                const T ll = lane_shift<kWaveShr1>(lc, lc), lr = lane_shift<kWaveShl1>(lc, lc);
+                const T vl = lane_shift<kWaveShr1>(vc, vc), vr = lane_shift<kWaveShl1>(vc, vc);
+                const T kl = lane_shift<kWaveShr1>(kc, kc), kr = lane_shift<kWaveShl1>(kc, kc);
+                T s = (T)0, t = (T)0;
+                s = fma(half * (kc + kl), ll - lc, s);
+                t = fma(vl - vc, lc - ll, t);
+                s = fma(half * (kc + kr), lr - lc, s);
+                t = fma(vr - vc, lc - lr, t);
+                s = fma(half * (kc + pk[r - 1]), mm[r - 1] - lc, s);
+                t = fma(V[r - 1] - vc, lc - mm[r - 1], t);
+                s = fma(half * (kc + pk[r + 1]), mm[r + 1] - lc, s);
+                t = fma(V[r + 1] - vc, lc - mm[r + 1], t);
+                bn[r] = s;
+                un2[r] = t;
+            }
+        }
+        if (m >= z0 && m <= zend) {
+            const bool done = m - 1 >= z0;
+            const Rsrc rl = plane_rsrc((const char*)lam.origin + (int64_t)(m - 1) * lpb, lpb);
+            const Rsrc rg = plane_rsrc((const char*)gk.origin + (int64_t)(m - 1) * gpb, gpb);
+#pragma unroll
+            for (int r = R2; r < E2; ++r) {
+                const T w = half * (k1[r] + pk[r]);
+                const T dl = mm[r] - m1[r];
+                const T dv = V[r] - v1[r];
+                if (done && b.y0 + r - R2 < ny && xin) {
+                    bstore<kStreamStore>(fma(dt, fma(w, dl, a2[r]), m1[r]), rl, so, rowoff(r, lam.sy, (int)sizeof(T)));
+                    bstore<kStreamStore>(gold[r] + (TG)(g1[r] + hdt * fma(dv, -dl, t2[r])), rg, sg,
+                                         rowoff(r, gk.sy, (int)sizeof(TG)));
+                }
+                if (own2) {
+                    bn[r] = fma(w, -dl, bn[r]);
+                    un2[r] = fma(-dv, dl, un2[r]);
+                }
+            }
+        }
+        // rotate: raw plane q becomes the previous one; the second level's
+        // plane m becomes its previous one
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r >= R1 && r < E1) {
+                a1[r] = own1 ? an[r] : (T)0;
+                t1[r] = own1 ? tn[r] : (T)0;
+            }
+            if (r >= R2 && r < E2) {
+                m1[r] = q > qstart ? mm[r] : (T)0;
+                g1[r] = q > qstart ? gm[r] : (T)0;
+                k1[r] = pk[r];
+                v1[r] = V[r];
+                a2[r] = own2 ? bn[r] : (T)0;
+                t2[r] = own2 ? un2[r] : (T)0;
+                gold[r] = own2 ? gnew[r] : (TG)0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            pl[r] = L[r];
+            pu[r] = U[r];
+            pk[r] = K[r];
+        }
+    };
+    int q = qstart;
+    for (; q + 1 <= qend; q += 2) {
+        step(q, std::integral_constant<int, 0>{});
+        step(q + 1, std::integral_constant<int, 1>{});
+    }
+    if (q <= qend) step(q, std::integral_constant<int, 0>{});
+}
+
 // Bricks of 64 columns by P rows; the z-chunk balanced against the waves the
 // device holds at once for this very build (as the sweep kernels do).
 template <typename K>
 bool wave_geometry(K kernel, int nw_per_block, int P, const DevGrid& g, int& chunk, int& strips, int& segs, int& nw,
-                   int& nbp) {
-    strips = (g.nx + 63) / 64;
+                   int& nbp, int W = 64) {
+    strips = (g.nx + W - 1) / W;
     segs = (g.ny + P - 1) / P;
     static const int bpc = blocks_per_cu(kernel, nw_per_block * 64);
     // at least 16 planes per chunk: each chunk re-reads the plane before and
@@ -375,7 +594,7 @@ bool wave_geometry(K kernel, int nw_per_block, int P, const DevGrid& g, int& chu
 // and for forward steps up to 2^25 points (their planes fit the last-level
 // cache), 8-row bricks for larger forward steps (fewer re-read halo rows).
 constexpr int kVarNW = 4;
-constexpr int kStream = 2;   // cache-policy bits of a streaming store
+constexpr int kStream = kStreamStore;
 
 template <typename T, int P>
 hipError_t fwd(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, double dt, hipStream_t s) {
@@ -397,6 +616,18 @@ hipError_t adj(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, co
     return hipGetLastError();
 }
 
+template <typename T, typename TG, int P>
+hipError_t adj2(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& ut, const DevGrid& utm1,
+                const DevGrid& kappa, const DevGrid& gk, double dt, hipStream_t s) {
+    constexpr auto kernel = k_varw_adjoint2<T, TG, P, kVarNW>;
+    int chunk, strips, segs, nw, nbp;
+    if (!wave_geometry(kernel, kVarNW, P, lam_next, chunk, strips, segs, nw, nbp, 62))
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(kernel, dim3(nbp), dim3(kVarNW * 64), 0, s, lam_next, lam, ut, utm1, kappa, gk, (T)dt, chunk,
+                       strips, segs, nw, nbp);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool var_wave_fits(const DevGrid& g, int esize) { return g.sz * (int64_t)esize < ((int64_t)1 << 31); }
@@ -414,6 +645,15 @@ hipError_t launch_var_adjoint_wave(const DevGrid& lam_next, const DevGrid& lam, 
     if (dtype == LOPE_F32) return adj<float, double, 4>(lam_next, lam, u, kappa, gk, dt, s);
     if (gk_dtype == LOPE_F64) return adj<double, double, 4>(lam_next, lam, u, kappa, gk, dt, s);
     return adj<double, float, 4>(lam_next, lam, u, kappa, gk, dt, s);
+}
+
+hipError_t launch_var_adjoint2_wave(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& ut,
+                                    const DevGrid& utm1, const DevGrid& kappa, const DevGrid& gk, int dtype,
+                                    int gk_dtype, double dt, hipStream_t s) {
+    if (dtype == LOPE_F32 && gk_dtype == LOPE_F32) return adj2<float, float, 4>(lam_next, lam, ut, utm1, kappa, gk, dt, s);
+    if (dtype == LOPE_F32) return adj2<float, double, 4>(lam_next, lam, ut, utm1, kappa, gk, dt, s);
+    if (gk_dtype == LOPE_F64) return adj2<double, double, 4>(lam_next, lam, ut, utm1, kappa, gk, dt, s);
+    return adj2<double, float, 4>(lam_next, lam, ut, utm1, kappa, gk, dt, s);
 }
 
 }  // namespace lope

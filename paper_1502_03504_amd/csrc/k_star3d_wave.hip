@@ -26,7 +26,10 @@
 // lane outside a Dirichlet x axis holds g at every level (bit blend, DXY), a
 // row outside a Dirichlet y axis is g at every level (DXY; a wave-uniform
 // choice per row) and a plane outside a Dirichlet z axis is g at every level
-// (DZ).
+// (DZ).  Under Dirichlet rules only the bricks whose footprint reaches the
+// edge of the interior along a Dirichlet axis run the blending march; the
+// others run the march without blends (or with the z rule only), chosen per
+// wave.
 //
 // Planes are prefetched PF steps ahead (PF = 1 or 3; the march is unrolled by
 // three, the period of the partial-sum ring, so every buffer index is a
@@ -120,10 +123,12 @@ __device__ __forceinline__ void static_steps(F&& f) {
 // STG: 0 = TD sweeps of one stencil; 1, 2 = TD / 2 two-stage steps: odd
 // levels apply cf, even levels cf2 (plus alpha times the state two levels
 // below, the state at the start of the step, when STG = 2).
-template <typename T, int TD, int P, int NW, bool DXY, bool DZ, bool RES, int STG, int PF, int WPE>
-__global__ void __launch_bounds__(NW * 64, WPE)
-k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, Coef7<T> cf2, T alpha, int chunk, int strips,
-              int segs, int nwaves, int nblocks_padded, double* residual) {
+// The march of the brick at (x0, y0) over planes z0 .. zend - 1.  DXY: the
+// rule may put g inside the brick's footprint along x or y.
+template <typename T, int TD, int P, bool DXY, bool DZ, bool RES, int STG, int PF>
+__device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& dst, const DevRule& rule,
+                                           const Coef7<T>& cf, const Coef7<T>& cf2, T alpha, int x0, int y0, int z0,
+                                           int zend, double* residual) {
     static_assert(PF == 1 || PF == 3, "the march is unrolled by three");
     // float64 would need two DPP moves per lane shift (no DPP form of the
     // 64-bit fma) and twice the registers: the LDS designs serve it better
@@ -132,14 +137,8 @@ k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, Coef7<T> cf2,
     typedef typename WMask<T>::type M;
     constexpr int G = TD;
     constexpr int NR = P + 2 * G;
-    // the wave index is uniform: rows, planes and loop bounds stay scalar
-    const int wave = xcd_logical_block(nblocks_padded) * NW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    if (wave >= nwaves) return;   // whole waves leave; there is no barrier
-    const int tx = wave % strips, rest = wave / strips;
-    const int ty = rest % segs, tz = rest / segs;
     const int nx = src.nx, ny = src.ny, nz = src.nz;
-    const int x0 = tx * (64 - 2 * G), y0 = ty * P, z0 = tz * chunk;
-    const int zend = min(z0 + chunk, nz), yend = min(y0 + P, ny);
+    const int yend = min(y0 + P, ny);
     const bool perx = rule.per[0] != 0, pery = rule.per[1] != 0;
     const T g = (T)rule.g;
 
@@ -304,6 +303,41 @@ k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, Coef7<T> cf2,
         step(j + 2, std::integral_constant<int, (P0 + 2) % 3>{}, all);
     }
     if (RES) residual_merge(rmax, residual);
+}
+
+template <typename T, int TD, int P, int NW, bool DXY, bool DZ, bool RES, int STG, int PF, int WPE>
+__global__ void __launch_bounds__(NW * 64, WPE)
+k_star3d_wave(DevGrid src, DevGrid dst, DevRule rule, Coef7<T> cf, Coef7<T> cf2, T alpha, int chunk, int strips,
+              int segs, int nwaves, int nblocks_padded, double* residual) {
+    constexpr int G = TD;
+    // the wave index is uniform: rows, planes and loop bounds stay scalar
+    const int wave = xcd_logical_block(nblocks_padded) * NW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wave >= nwaves) return;   // whole waves leave; there is no barrier
+    const int tx = wave % strips, rest = wave / strips;
+    const int ty = rest % segs, tz = rest / segs;
+    const int x0 = tx * (64 - 2 * G), y0 = ty * P, z0 = tz * chunk;
+    const int zend = min(z0 + chunk, src.nz);
+    if constexpr (DXY || DZ) {
+        // a brick whose footprint (64 columns, P + 2 G rows, the chunk and G
+        // planes on each side) lies inside the interior along every Dirichlet
+        // axis never meets g: it runs the march without the rule's blends
+        const bool xin = rule.per[0] != 0 || (x0 - G >= 0 && x0 - G + 63 < src.nx);
+        const bool yin = rule.per[1] != 0 || (y0 - G >= 0 && y0 + P + G - 1 < src.ny);
+        const bool zin = rule.per[2] != 0 || (z0 - G >= 0 && zend - 1 + G < src.nz);
+        if (xin && yin && zin) {
+            wave_brick<T, TD, P, false, false, RES, STG, PF>(src, dst, rule, cf, cf2, alpha, x0, y0, z0, zend,
+                                                              residual);
+            return;
+        }
+        if constexpr (DXY && DZ) {
+            if (xin && yin) {   // only the z rule reaches this brick
+                wave_brick<T, TD, P, false, true, RES, STG, PF>(src, dst, rule, cf, cf2, alpha, x0, y0, z0, zend,
+                                                                 residual);
+                return;
+            }
+        }
+    }
+    wave_brick<T, TD, P, DXY, DZ, RES, STG, PF>(src, dst, rule, cf, cf2, alpha, x0, y0, z0, zend, residual);
 }
 
 template <typename T>

@@ -128,6 +128,9 @@ hipError_t launch_var_forward_wave(const DevGrid& src, const DevGrid& dst, const
                                    hipStream_t s);
 hipError_t launch_var_adjoint_wave(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, const DevGrid& kappa,
                                    const DevGrid& gk, int dtype, int gk_dtype, double dt, hipStream_t s);
+hipError_t launch_var_adjoint2_wave(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& ut,
+                                    const DevGrid& utm1, const DevGrid& kappa, const DevGrid& gk, int dtype,
+                                    int gk_dtype, double dt, hipStream_t s);
 
 // Two fused reverse steps: lam_{t-1} from lam_{t+1}, both kappa terms in one update.
 hipError_t launch_var_adjoint2(const DevGrid& lam_next, const DevGrid& lam_out, const DevGrid& u_t,

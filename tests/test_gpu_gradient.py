@@ -74,7 +74,9 @@ def test_gradient_float64_matches_oracle():
 
 
 def test_checkpoint_interval_does_not_change_gradient():
-    """Both gradients are bitwise independent of the checkpoint interval."""
+    """dL/du0 is bitwise independent of the interval; dL/dkappa too for even
+    intervals (every step pair fused); an odd interval splits some pairs,
+    which changes only the order of the float32 accumulator's additions."""
     c, u0, k, tg = _case(24, 60, seed=3)
     ref = None
     for every in (20, 2, 60, 1, 7):
@@ -85,7 +87,10 @@ def test_checkpoint_interval_does_not_change_gradient():
             continue
         assert cur[0] == ref[0]
         np.testing.assert_array_equal(cur[1], ref[1])
-        np.testing.assert_array_equal(cur[2], ref[2])
+        if every % 2 == 0:
+            np.testing.assert_array_equal(cur[2], ref[2])
+        else:
+            assert rel_err(cur[2], ref[2]) <= 1e-6
 
 
 def test_fused_reverse_pair_matches_two_steps_and_oracle():
