@@ -68,7 +68,8 @@ def test_apply_matches_oracle(ndim, r, shape_kind, dtype):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-@pytest.mark.parametrize("ndim,r,shape_kind", [(2, 1, "box"), (2, 1, "star"), (3, 1, "star"), (3, 4, "star")])
+@pytest.mark.parametrize("ndim,r,shape_kind", [(2, 1, "box"), (2, 1, "star"), (3, 1, "star"), (3, 2, "star"),
+                                               (3, 3, "star"), (3, 4, "star")])
 def test_every_variant_and_depth_agrees(ndim, r, shape_kind, dtype):
     """All tiles, depths and chunk sizes give identical values (same fma
     order), and match the oracle after n sweeps."""
