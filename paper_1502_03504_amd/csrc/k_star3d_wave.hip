@@ -29,7 +29,9 @@
 // (DZ).  Under Dirichlet rules only the bricks whose footprint reaches the
 // edge of the interior along a Dirichlet axis run the blending march; the
 // others run the march without blends (or with the z rule only), chosen per
-// wave.
+// wave.  The z rule itself only touches the warm-up steps and the last few
+// steps of a march (those that load or complete a plane past the z edge), so
+// the steps in between run without it.
 //
 // Planes are prefetched PF steps ahead (PF = 1 or 3; the march is unrolled by
 // three, the period of the partial-sum ring, so every buffer index is a
@@ -167,11 +169,13 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
     const char* dp = (const char*)dst.origin;
     const int64_t szb = src.sz * (int64_t)sizeof(T), dszb = dst.sz * (int64_t)sizeof(T);
     // Plane q of level 0 (every row loaded: the index is wrapped, or clamped
-    // and then replaced by g outside a Dirichlet z axis).
-    auto load_plane = [&](int q, T (&v)[NR]) {
-        const int qw = DZ ? min(max(q, 0), nz - 1) : wrap_index(q, nz);
+    // and then replaced by g outside a Dirichlet z axis).  ZR: a Dirichlet z
+    // rule may apply to q (else q is inside or wrapped).
+    auto load_plane = [&](int q, T (&v)[NR], auto zrule) __attribute__((always_inline)) {
+        constexpr bool ZR = decltype(zrule)::value;
+        const int qw = ZR ? min(max(q, 0), nz - 1) : wrap_index(q, nz);
         const __amdgpu_buffer_rsrc_t rs = plane_rsrc(sp + qw * szb, szb);
-        const bool gz = DZ && (q < 0 || q >= nz);
+        const bool gz = ZR && (q < 0 || q >= nz);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const T t = buffer_load<T>(rs, boff[r]);
@@ -192,7 +196,7 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
     const int jstart = z0 - TD, jend = zend - 1 + TD;
     T pf[PF][NR];
 #pragma unroll
-    for (int q = 0; q < PF; ++q) load_plane(jstart + q, pf[q]);
+    for (int q = 0; q < PF; ++q) load_plane(jstart + q, pf[q], std::integral_constant<bool, DZ>{});
 
     const unsigned xoff = (unsigned)(keep ? gx : 0) * (unsigned)sizeof(T);
     double rmax = 0.0;   // RES: this lane's maximum change over its outputs
@@ -204,10 +208,12 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
     // level 0 is the plane in pf[u % PF]; once consumed, that buffer takes the
     // plane PF steps ahead (past the end: a repeat of the last plane, never
     // used).  Only levels k < KM run: during the first 2*TD steps level k+1
-    // has nothing valid to start before step 2k, so those steps skip it.
-    auto step = [&](int j, auto phase, auto kmax) __attribute__((always_inline)) {
+    // has nothing valid to start before step 2k, so those steps skip it.  ZR:
+    // the step may load or complete a plane outside a Dirichlet z axis.
+    auto step = [&](int j, auto phase, auto kmax, auto zrule) __attribute__((always_inline)) {
         constexpr int u = decltype(phase)::value;
         constexpr int KM = decltype(kmax)::value;
+        constexpr bool ZR = decltype(zrule)::value;
         T cur[NR];
         T base[NR];   // STG = 2: the state at the start of the step (level k-1 for an even level k+1)
 #pragma unroll
@@ -253,10 +259,10 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
                 // alpha * (that plane of level k-1), completed this step
                 nw[r] = with_alpha ? fma(c.c[0], bl[r], alpha * base[r]) : c.c[0] * bl[r];
             }
-            if (k == 0) load_plane(min(j + PF, jend), pf[u % PF]);
+            if (k == 0) load_plane(min(j + PF, jend), pf[u % PF], zrule);
             // the rule on the completed plane p of level k+1
             const int p = j - k - 1;
-            const bool gz = DZ && (p < 0 || p >= nz);
+            const bool gz = ZR && (p < 0 || p >= nz);
 #pragma unroll
             for (int r = k + 1; r < NR - 1 - k; ++r) {
                 T v = DXY ? wblend(live, nxt[r], g) : nxt[r];
@@ -290,17 +296,40 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
     static_steps<0, 2 * TD>([&](auto st) __attribute__((always_inline)) {
         constexpr int sidx = decltype(st)::value;
         constexpr int km = sidx / 2 + 1 < TD ? sidx / 2 + 1 : TD;
-        step(jstart + sidx, std::integral_constant<int, sidx % 3>{}, std::integral_constant<int, km>{});
+        step(jstart + sidx, std::integral_constant<int, sidx % 3>{}, std::integral_constant<int, km>{},
+             std::integral_constant<bool, DZ>{});
     });
     // then every level, three steps per iteration with the phases continuing
     constexpr int P0 = (2 * TD) % 3;
     const std::integral_constant<int, TD> all{};
-    for (int j = jstart + 2 * TD; j <= jend; j += 3) {
-        step(j, std::integral_constant<int, P0>{}, all);
+    const std::integral_constant<int, P0> ph0{};
+    const std::integral_constant<int, (P0 + 1) % 3> ph1{};
+    const std::integral_constant<int, (P0 + 2) % 3> ph2{};
+    // Under a Dirichlet rule, whole groups of three steps first.  After the
+    // warm-up every completed plane j - k - 1 is at least z0, so a Dirichlet
+    // z axis only reaches the steps that load a plane at nz or beyond, or
+    // complete one there: the groups before those (the last loaded plane
+    // j + 2 + PF < nz) run without the z rule.  Then the remaining steps
+    // (under the rule).  The register allocation of the blending march fits
+    // two waves per SIMD in this form; the plain march fits in the single
+    // loop below.
+    int j = jstart + 2 * TD;
+    if constexpr (DXY || DZ) {
+        const std::integral_constant<bool, false> inside{};
+        const int jsafe = (DZ ? min(jend, nz - 1 - PF) : jend) - 2;
+        for (; j <= jsafe; j += 3) {
+            step(j, ph0, all, inside);
+            step(j + 1, ph1, all, inside);
+            step(j + 2, ph2, all, inside);
+        }
+    }
+    const std::integral_constant<bool, DZ> zr{};
+    for (; j <= jend; j += 3) {
+        step(j, ph0, all, zr);
         if (j + 1 > jend) break;
-        step(j + 1, std::integral_constant<int, (P0 + 1) % 3>{}, all);
+        step(j + 1, ph1, all, zr);
         if (j + 2 > jend) break;
-        step(j + 2, std::integral_constant<int, (P0 + 2) % 3>{}, all);
+        step(j + 2, ph2, all, zr);
     }
     if (RES) residual_merge(rmax, residual);
 }
