@@ -227,6 +227,9 @@ def measure_workloads(reps=3):
     # (name, inputs, sweeps per pass requested: 0 = the tuned default)
     cases = [("heat3d_7pt_512^3_f32_periodic_1000_sweeps_one_sweep_per_pass",
               lambda: synth.case_heat3d(n=512, dtype=np.float32), 1),
+             ("heat3d_7pt_512^3_f32_dirichlet_1000_sweeps",
+              lambda: synth.case_heat3d(n=512, dtype=np.float32)._replace(
+                  bc=synth.Boundary((synth.DIRICHLET,) * 3, 0.0)), 0),
              ("heat2d_5pt_256^2_f64_dirichlet_100_sweeps", synth.case_heat2d, 0),
              ("heat3d_7pt_256^3_f64_periodic_1000_sweeps", lambda: synth.case_heat3d(n=256, dtype=np.float64), 0),
              ("box9_8192^2_f32_periodic_1000_sweeps", synth.case_box9, 0),

@@ -1,5 +1,5 @@
 // Variable-coefficient diffusion on a periodic 3D grid, one wavefront per
-// brick: the forward step and the one-step reverse.
+// brick: the forward step, the one-step reverse and two reverse steps fused.
 //
 //   forward:  u'_x = u_x + dt * sum_q K_q (u_q - u_x),   K_q = (kappa_x + kappa_q) / 2
 //   reverse:  lam_x = lam'_x + dt * sum_q K_q (lam'_q - lam'_x)
@@ -11,11 +11,11 @@
 // the current plane in registers (the y neighbours are the rows above and
 // below).  The x neighbours come from lanes l-1 and l+1 by DPP lane shifts;
 // the two columns just outside the wave (x0 - 1 for lane 0, x0 + 64 for lane
-// 63) arrive in one extra load per plane and array: lane i < P loads the left
-// outside column of row i + 1, lane 32 + i the right one, and the row's shift
-// takes its outside value from there (read into a scalar register).  Every
-// index is wrapped (the grids are periodic), so lanes past a ragged x end
-// hold wrapped columns that are never stored.
+// 63) arrive in one extra load per plane and array that packs them into
+// lanes, laid out so that one DPP row rotation brings a row's two outside
+// values to lanes 0 and 63, where the shifts keep them.  Every index is
+// wrapped (the grids are periodic), so lanes past a ragged x end hold
+// wrapped columns that are never stored.
 //
 // The z direction is the march: when plane j arrives its in-plane terms
 // (x-, x+, y-, y+) start its sums; then the face between planes j-1 and j is
