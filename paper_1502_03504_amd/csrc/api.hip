@@ -1256,8 +1256,8 @@ int lope_apply_var_adjoint2(const lope_grid* lam_next, const lope_grid* lam, con
     const DevGrid gn = dev_grid(lam_next), gl = dev_grid(lam), gu = dev_grid(u_t), gv = dev_grid(u_tm1),
                   gk = dev_grid(vc->kappa), gg = dev_grid(gkappa);
     const int es = (int)elem_size(lam_next->dtype);
-    const bool wave = var_wave_fits(gn, es) && var_wave_fits(gl, es) && var_wave_fits(gu, es) &&
-                      var_wave_fits(gv, es) && var_wave_fits(gk, es) && var_wave_fits(gg, (int)elem_size(gkappa->dtype));
+    const bool wave = var_pair_wave_fits(gn, gu, gv, gk, es) && var_wave_fits(gl, es) &&
+                      var_wave_fits(gg, (int)elem_size(gkappa->dtype));
     log_line("diffusion reverse pair on %dx%dx%d: %s", gn.nx, gn.ny, gn.nz, wave ? "k_varw_adjoint2" : "k_var_adjoint2");
     const hipError_t e =
         wave ? launch_var_adjoint2_wave(gn, gl, gu, gv, gk, gg, lam_next->dtype, gkappa->dtype, vc->dt, (hipStream_t)stream)

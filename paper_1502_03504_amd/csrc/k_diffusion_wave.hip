@@ -86,6 +86,26 @@ __device__ __forceinline__ double lane_shift(double v, double old) {
         (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
+// The same shifts where the lane past the wave's end is not used: that lane
+// reads 0, and the compiler may fold the move into the instruction using it.
+template <int CTRL>
+__device__ __forceinline__ float lane_shift_free(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift_free(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// Plane index i wrapped into [0, n) (periodic z; i is wave-uniform and at
+// most a few planes outside).
+__device__ __forceinline__ int plane_wrap(int i, int n) {
+    while (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+}
 // Rotation within every row of 16 lanes: lane i of a row receives lane
 // (i + a) mod 16 of the same row (a = 0..15; DPP row_ror by 16 - a).
 template <int A>
@@ -165,6 +185,19 @@ struct Cols {
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = bload<T, AUX>(rs, xo, row[r]);
         e = bload<T, AUX>(rs, eo, 0);
+    }
+    // the same for another array of this very layout, based at `other`, plane
+    // qw (already wrapped)
+    __device__ __forceinline__ void load_at(const char* other, int qw, T (&v)[NR], T& e) const {
+        const Rsrc rs = plane_rsrc(other + (int64_t)qw * pbytes, pbytes);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = bload<T>(rs, xo, row[r]);
+        e = bload<T>(rs, eo, 0);
+    }
+    __device__ __forceinline__ void load_rows_at(const char* other, int qw, T (&v)[NR]) const {
+        const Rsrc rs = plane_rsrc(other + (int64_t)qw * pbytes, pbytes);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = bload<T>(rs, xo, row[r]);
     }
 };
 
@@ -389,8 +422,20 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
 // brick's P rows plus one on each side, loaded with two more on each side.
 // Along z the first level completes raw plane q - 1 when plane q arrives
 // (the shared face as in the one-step kernel), and the second level, fed by
-// those completed planes, completes plane q - 2.  u_{t-1} is loaded one plane
-// behind lam'', u_t and kappa.
+// those completed planes, completes plane q - 2; its face coefficient
+// between planes q - 2 and q - 1 is the first level's of the step before.
+//
+// Every plane and every partial sum lives in a ring of three slots indexed
+// by the step's phase (the march is unrolled by three), so no value moves
+// between registers.  Every step is the same code: planes before and after
+// the chunk are loaded (wrapped) and computed like the others, and their
+// results never reach a store, because a store (and the load of the old
+// gradient) whose plane lies outside the chunk goes through a resource of no
+// bytes and a lane or row without an output uses the offset 2^31; the range
+// check drops both.  With the same number of memory operations in every
+// step the waits for a plane's loads count exactly what was issued after
+// them.  The four inputs share one layout (the launcher checks), so one row
+// table addresses them all.
 template <typename T, typename TG, int P, int NW>
 __global__ void __launch_bounds__(NW * 64)
 k_varw_adjoint2(DevGrid lnext, DevGrid lam, DevGrid ut, DevGrid utm1, DevGrid kap, DevGrid gk, T dt, int chunk,
@@ -399,175 +444,194 @@ k_varw_adjoint2(DevGrid lnext, DevGrid lam, DevGrid ut, DevGrid utm1, DevGrid ka
     constexpr int R1 = 1, E1 = NR - 1;   // first-level rows [R1, E1)
     constexpr int R2 = 2, E2 = NR - 2;   // second-level rows [R2, E2): the outputs
     constexpr int W = 62;
+    constexpr unsigned kDrop = 0x80000000u;   // past every plane (planes are below 2^31 bytes)
     Brick b;
     if (!brick_of(lnext, P, chunk, strips, segs, nwaves, nbp, NW, b, W)) return;
-    Cols<T, NR> cl, cu, ck, cv;
-    cl.init(lnext, b.x0 - 1, b.y0 - 2, E1 - R1);
-    cu.init(ut, b.x0 - 1, b.y0 - 2, E1 - R1);
-    ck.init(kap, b.x0 - 1, b.y0 - 2, E1 - R1);
-    cv.init(utm1, b.x0 - 1, b.y0 - 2, E1 - R1);
+    Cols<T, NR> c;
+    c.init(lnext, b.x0 - 1, b.y0 - 2, E1 - R1);
+    const char* const bl = (const char*)lnext.origin;
+    const char* const bu = (const char*)ut.origin;
+    const char* const bk = (const char*)kap.origin;
+    const char* const bv = (const char*)utm1.origin;
     const int lane = threadIdx.x & 63;
     const int nz = lnext.nz, ny = lnext.ny;
     const int gx = b.x0 - 1 + lane;
     const bool xin = lane >= 1 && lane <= W && gx < lnext.nx;   // an output lane
-    const unsigned so = (unsigned)(xin ? gx : 0) * (unsigned)sizeof(T);
-    const unsigned sg = (unsigned)(xin ? gx : 0) * (unsigned)sizeof(TG);
     const int64_t lpb = lam.sz * (int64_t)sizeof(T), gpb = gk.sz * (int64_t)sizeof(TG);
     const T half = (T)0.5, hdt = (T)0.5 * dt;
     const int z0 = b.z0, zend = b.zend;
-
-    // raw planes: current and in flight (lam'', u_t, kappa with outside columns)
-    T l[2][NR], u[2][NR], k[2][NR], el[2], eu[2], ek[2];
-    T v[2][NR];                    // u_{t-1}: plane q - 1 and the one in flight
-    T pl[NR], pu[NR], pk[NR];      // raw plane q - 1 (first-level rows)
-    T a1[NR], t1[NR];              // first level, plane q - 1: partial sums
-    T m1[NR], k1[NR], v1[NR];      // second level's plane m - 1: lam_t, kappa, u_{t-1}
-    T a2[NR], t2[NR], g1[NR];      // second level, plane m - 1: partial sums, hdt*G1
-    TG gold[NR];                   // kappa gradient of plane m - 1
+    // output rows: in-plane offsets of this lane's column (kDrop where there
+    // is no output), wave-uniform row offsets
+    unsigned vol[NR], vog[NR];
+    int srl[NR], srg[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        pl[r] = pu[r] = pk[r] = a1[r] = t1[r] = m1[r] = k1[r] = v1[r] = a2[r] = t2[r] = g1[r] = (T)0;
-        gold[r] = (TG)0;
-        v[0][r] = v[1][r] = (T)0;
+    for (int r = R2; r < E2; ++r) {
+        const int y = b.y0 + r - R2;
+        const bool ok = xin && y < ny;
+        vol[r] = ok ? (unsigned)gx * (unsigned)sizeof(T) : kDrop;
+        vog[r] = ok ? (unsigned)gx * (unsigned)sizeof(TG) : kDrop;
+        const int yr = y < ny ? y : 0;
+        srl[r] = (int)((unsigned)yr * (unsigned)lam.sy * (unsigned)sizeof(T));
+        srg[r] = (int)((unsigned)yr * (unsigned)gk.sy * (unsigned)sizeof(TG));
+    }
+
+    // rings of three, slot = phase of the plane's step
+    T l[3][NR], u[3][NR], k[3][NR], el[3], eu[3], ek[3];   // raw lam'', u_t, kappa
+    T v[3][NR];                    // u_{t-1}
+    T a1[3][NR], t1[3][NR];        // first level: partial sums of its plane
+    T m1[3][NR], g1[3][NR];        // first level's completed plane: lam_t, hdt*G1
+    T ws[3][NR];                   // first level's face coefficient (second level's z- face)
+    T a2[3][NR], t2[3][NR];        // second level: partial sums of its plane
+    TG gold[3][NR];                // kappa gradient of the second level's plane
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            l[s][r] = u[s][r] = k[s][r] = v[s][r] = (T)0;
+            a1[s][r] = t1[s][r] = m1[s][r] = g1[s][r] = ws[s][r] = a2[s][r] = t2[s][r] = (T)0;
+            gold[s][r] = (TG)0;
+        }
+        el[s] = eu[s] = ek[s] = (T)0;
     }
     const int qstart = z0 - 2, qend = zend + 1;
-    cl.load(qstart, nz, l[0], el[0]);
-    cu.load(qstart, nz, u[0], eu[0]);
-    ck.load(qstart, nz, k[0], ek[0]);
+    {
+        const int qw = plane_wrap(qstart, nz);
+        c.load_at(bl, qw, l[0], el[0]);
+        c.load_at(bu, qw, u[0], eu[0]);
+        c.load_at(bk, qw, k[0], ek[0]);
+    }
 
-    auto rowoff = [&](int r, int64_t sy, int es) { return (int)((unsigned)(b.y0 + r - R2) * (unsigned)sy * (unsigned)es); };
-    auto step = [&](int q, auto cur_c) __attribute__((always_inline)) {
-        constexpr int C = decltype(cur_c)::value, N = C ^ 1;
-        if (q + 1 <= qend) {
-            cl.load(q + 1, nz, l[N], el[N]);
-            cu.load(q + 1, nz, u[N], eu[N]);
-            ck.load(q + 1, nz, k[N], ek[N]);
+    // step q, phase C: plane q in slot C, q - 1 in slot PV, q + 1 (and q - 2) in slot NX
+    auto step = [&](int q, auto phase) __attribute__((always_inline)) {
+        constexpr int C = decltype(phase)::value, PV = (C + 2) % 3, NX = (C + 1) % 3;
+        const int m = q - 1;
+        const int qw = plane_wrap(q, nz), qn = qw + 1 < nz ? qw + 1 : 0;
+        c.load_at(bl, qn, l[NX], el[NX]);
+        c.load_at(bu, qn, u[NX], eu[NX]);
+        c.load_at(bk, qn, k[NX], ek[NX]);
+        c.load_rows_at(bv, qw, v[C]);
+        {
+            // the old gradient of plane m (added when m is completed, next step)
+            const bool own2 = m >= z0 && m < zend;
+            const Rsrc rg = plane_rsrc((const char*)gk.origin + (int64_t)(own2 ? m : z0) * gpb, own2 ? gpb : 0);
+#pragma unroll
+            for (int r = R2; r < E2; ++r) gold[C][r] = bload<TG>(rg, vog[r], srg[r]);
         }
-        if (q <= zend) cv.load_rows(q, nz, v[N]);   // u_{t-1} at plane q, used at step q + 1
         const T(&L)[NR] = l[C];
         const T(&U)[NR] = u[C];
         const T(&K)[NR] = k[C];
-        const T(&V)[NR] = v[C];        // u_{t-1} at plane q - 1
-        // first level, plane q: in-plane terms
+        const T(&pl)[NR] = l[PV];
+        const T(&pu)[NR] = u[PV];
+        const T(&pk)[NR] = k[PV];
+        const T(&V)[NR] = v[PV];       // u_{t-1} at plane m
+        const T(&V1)[NR] = v[NX];      // u_{t-1} at plane m - 1
+        // first level, plane q: in-plane terms.  The face between rows r and
+        // r + 1 is formed once and serves both (its difference negated for
+        // row r + 1, exactly the value that row would form).
+        T fw[NR], fl[NR], fu[NR];
+#pragma unroll
+        for (int r = R1 - 1; r < E1; ++r) {
+            fw[r] = half * (K[r + 1] + K[r]);
+            fl[r] = L[r + 1] - L[r];
+            fu[r] = U[r + 1] - U[r];
+        }
         T an[NR], tn[NR];
-        const bool own1 = q >= z0 - 1 && q <= zend;
-        if (own1) {
-            static_for<R1, E1>([&](auto rc) __attribute__((always_inline)) {
-                constexpr int r = decltype(rc)::value;
-                const T lc = L[r], uc = U[r], kc = K[r];
-                T ll, lr, ul, ur, kl, kr;
-                x_neighbours<r>(L, el[C], ll, lr);
-                x_neighbours<r>(U, eu[C], ul, ur);
-                x_neighbours<r>(K, ek[C], kl, kr);
-                T s = (T)0, t = (T)0;
-                s = fma(half * (kc + kl), ll - lc, s);
-                t = fma(ul - uc, lc - ll, t);
-                s = fma(half * (kc + kr), lr - lc, s);
-                t = fma(ur - uc, lc - lr, t);
-                s = fma(half * (kc + K[r - 1]), L[r - 1] - lc, s);
-                t = fma(U[r - 1] - uc, lc - L[r - 1], t);
-                s = fma(half * (kc + K[r + 1]), L[r + 1] - lc, s);
-                t = fma(U[r + 1] - uc, lc - L[r + 1], t);
-                an[r] = s;
-                tn[r] = t;
-            });
-        }
+        static_for<R1, E1>([&](auto rc) __attribute__((always_inline)) {
+            constexpr int r = decltype(rc)::value;
+            const T lc = L[r], uc = U[r], kc = K[r];
+            T ll, lr, ul, ur, kl, kr;
+            x_neighbours<r>(L, el[C], ll, lr);
+            x_neighbours<r>(U, eu[C], ul, ur);
+            x_neighbours<r>(K, ek[C], kl, kr);
+            T s = (T)0, t = (T)0;
+            s = fma(half * (kc + kl), ll - lc, s);
+            t = fma(ul - uc, lc - ll, t);
+            s = fma(half * (kc + kr), lr - lc, s);
+            t = fma(ur - uc, lc - lr, t);
+            s = fma(fw[r - 1], -fl[r - 1], s);
+            t = fma(-fu[r - 1], fl[r - 1], t);
+            s = fma(fw[r], fl[r], s);
+            t = fma(fu[r], -fl[r], t);
+            an[r] = s;
+            tn[r] = t;
+        });
         // first level: the face between raw planes q - 1 and q completes
-        // plane m = q - 1 (lam_t and hdt*G1 there)
-        T mm[NR], gm[NR];
-        const int m = q - 1;
-        if (q > qstart) {
+        // plane m (lam_t and hdt*G1 there)
+        T(&mm)[NR] = m1[C];
 #pragma unroll
-            for (int r = R1; r < E1; ++r) {
-                const T w = half * (pk[r] + K[r]);
-                const T dl = L[r] - pl[r];
-                const T du = U[r] - pu[r];
-                mm[r] = fma(dt, fma(w, dl, a1[r]), pl[r]);
-                gm[r] = hdt * fma(du, -dl, t1[r]);
-                if (own1) {
-                    an[r] = fma(w, -dl, an[r]);
-                    tn[r] = fma(-du, dl, tn[r]);
-                }
-            }
-        }
-        // second level at plane m: in-plane terms (rows R2..E2, lanes 1..62),
-        // then the face between m - 1 and m, which completes m - 1
-        T bn[NR], un2[NR];
-        TG gnew[NR];
-        const bool own2 = m >= z0 && m < zend;
-        if (own2) {
-            const Rsrc rgj = plane_rsrc((const char*)gk.origin + (int64_t)m * gpb, gpb);
-#pragma unroll
-            for (int r = R2; r < E2; ++r) {
-                gnew[r] = (b.y0 + r - R2 < ny && xin) ? bload<TG>(rgj, sg, rowoff(r, gk.sy, (int)sizeof(TG))) : (TG)0;
-                const T lc = mm[r], vc = V[r], kc = pk[r];
-                const T ll = lane_shift<kWaveShr1>(lc, lc), lr = lane_shift<kWaveShl1>(lc, lc);
-                const T vl = lane_shift<kWaveShr1>(vc, vc), vr = lane_shift<kWaveShl1>(vc, vc);
-                const T kl = lane_shift<kWaveShr1>(kc, kc), kr = lane_shift<kWaveShl1>(kc, kc);
-                T s = (T)0, t = (T)0;
-                s = fma(half * (kc + kl), ll - lc, s);
-                t = fma(vl - vc, lc - ll, t);
-                s = fma(half * (kc + kr), lr - lc, s);
-                t = fma(vr - vc, lc - lr, t);
-                s = fma(half * (kc + pk[r - 1]), mm[r - 1] - lc, s);
-                t = fma(V[r - 1] - vc, lc - mm[r - 1], t);
-                s = fma(half * (kc + pk[r + 1]), mm[r + 1] - lc, s);
-                t = fma(V[r + 1] - vc, lc - mm[r + 1], t);
-                bn[r] = s;
-                un2[r] = t;
-            }
-        }
-        if (m >= z0 && m <= zend) {
-            const bool done = m - 1 >= z0;
-            const Rsrc rl = plane_rsrc((const char*)lam.origin + (int64_t)(m - 1) * lpb, lpb);
-            const Rsrc rg = plane_rsrc((const char*)gk.origin + (int64_t)(m - 1) * gpb, gpb);
-#pragma unroll
-            for (int r = R2; r < E2; ++r) {
-                const T w = half * (k1[r] + pk[r]);
-                const T dl = mm[r] - m1[r];
-                const T dv = V[r] - v1[r];
-                if (done && b.y0 + r - R2 < ny && xin) {
-                    bstore<kStreamStore>(fma(dt, fma(w, dl, a2[r]), m1[r]), rl, so, rowoff(r, lam.sy, (int)sizeof(T)));
-                    bstore<kStreamStore>(gold[r] + (TG)(g1[r] + hdt * fma(dv, -dl, t2[r])), rg, sg,
-                                         rowoff(r, gk.sy, (int)sizeof(TG)));
-                }
-                if (own2) {
-                    bn[r] = fma(w, -dl, bn[r]);
-                    un2[r] = fma(-dv, dl, un2[r]);
-                }
-            }
-        }
-        // rotate: raw plane q becomes the previous one; the second level's
-        // plane m becomes its previous one
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (r >= R1 && r < E1) {
-                a1[r] = own1 ? an[r] : (T)0;
-                t1[r] = own1 ? tn[r] : (T)0;
-            }
+        for (int r = R1; r < E1; ++r) {
+            const T w = half * (pk[r] + K[r]);
+            const T dl = L[r] - pl[r];
+            const T du = U[r] - pu[r];
+            mm[r] = fma(dt, fma(w, dl, a1[PV][r]), pl[r]);
             if (r >= R2 && r < E2) {
-                m1[r] = q > qstart ? mm[r] : (T)0;
-                g1[r] = q > qstart ? gm[r] : (T)0;
-                k1[r] = pk[r];
-                v1[r] = V[r];
-                a2[r] = own2 ? bn[r] : (T)0;
-                t2[r] = own2 ? un2[r] : (T)0;
-                gold[r] = own2 ? gnew[r] : (TG)0;
+                g1[C][r] = hdt * fma(du, -dl, t1[PV][r]);
+                ws[C][r] = w;
             }
+            a1[C][r] = fma(w, -dl, an[r]);
+            t1[C][r] = fma(-du, dl, tn[r]);
         }
+        // second level at plane m: in-plane terms (rows R2..E2, lanes 1..62).
+        // Faces shared as above: along y between rows, along x with the lane
+        // to the left (its x+ face is this lane's x- face; lanes 0 and 63 hold
+        // no output, so their shifted values are unused).
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            pl[r] = L[r];
-            pu[r] = U[r];
-            pk[r] = K[r];
+        for (int r = R2 - 1; r < E2; ++r) {
+            fw[r] = half * (pk[r + 1] + pk[r]);
+            fl[r] = mm[r + 1] - mm[r];
+            fu[r] = V[r + 1] - V[r];
+        }
+        T bn[NR], un2[NR];
+#pragma unroll
+        for (int r = R2; r < E2; ++r) {
+            const T lc = mm[r], vc = V[r], kc = pk[r];
+            const T lr = lane_shift_free<kWaveShl1>(lc), vr = lane_shift_free<kWaveShl1>(vc);
+            const T kr = lane_shift_free<kWaveShl1>(kc);
+            const T xw = half * (kc + kr), xl = lr - lc, xv = vr - vc;   // x+ face
+            const T wl = lane_shift_free<kWaveShr1>(xw), dl = lane_shift_free<kWaveShr1>(xl);
+            const T dv = lane_shift_free<kWaveShr1>(xv);                  // x- face
+            T s = (T)0, t = (T)0;
+            s = fma(wl, -dl, s);
+            t = fma(-dv, dl, t);
+            s = fma(xw, xl, s);
+            t = fma(xv, -xl, t);
+            s = fma(fw[r - 1], -fl[r - 1], s);
+            t = fma(-fu[r - 1], fl[r - 1], t);
+            s = fma(fw[r], fl[r], s);
+            t = fma(fu[r], -fl[r], t);
+            bn[r] = s;
+            un2[r] = t;
+        }
+        // second level: the face between m - 1 and m completes plane m - 1
+        {
+            const int p = m - 1;
+            const bool done = p >= z0 && p < zend;
+            const int pc = done ? p : z0;
+            const Rsrc rl = plane_rsrc((const char*)lam.origin + (int64_t)pc * lpb, done ? lpb : 0);
+            const Rsrc rg = plane_rsrc((const char*)gk.origin + (int64_t)pc * gpb, done ? gpb : 0);
+#pragma unroll
+            for (int r = R2; r < E2; ++r) {
+                const T w = ws[PV][r];
+                const T dl = mm[r] - m1[PV][r];
+                const T dv = V[r] - V1[r];
+                bstore<kStreamStore>(fma(dt, fma(w, dl, a2[PV][r]), m1[PV][r]), rl, vol[r], srl[r]);
+                bstore<kStreamStore>(gold[PV][r] + (TG)(g1[PV][r] + hdt * fma(dv, -dl, t2[PV][r])), rg, vog[r],
+                                         srg[r]);
+                a2[C][r] = fma(w, -dl, bn[r]);
+                t2[C][r] = fma(-dv, dl, un2[r]);
+            }
         }
     };
     int q = qstart;
-    for (; q + 1 <= qend; q += 2) {
+    for (; q + 2 <= qend; q += 3) {
         step(q, std::integral_constant<int, 0>{});
         step(q + 1, std::integral_constant<int, 1>{});
+        step(q + 2, std::integral_constant<int, 2>{});
     }
-    if (q <= qend) step(q, std::integral_constant<int, 0>{});
+    if (q <= qend) {
+        step(q, std::integral_constant<int, 0>{});
+        if (q + 1 <= qend) step(q + 1, std::integral_constant<int, 1>{});
+    }
 }
 
 // Bricks of 64 columns by P rows; the z-chunk balanced against the waves the
@@ -619,6 +683,7 @@ hipError_t adj(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, co
 template <typename T, typename TG, int P>
 hipError_t adj2(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& ut, const DevGrid& utm1,
                 const DevGrid& kappa, const DevGrid& gk, double dt, hipStream_t s) {
+    if (!var_pair_wave_fits(lam_next, ut, utm1, kappa, (int)sizeof(T))) return hipErrorInvalidValue;
     constexpr auto kernel = k_varw_adjoint2<T, TG, P, kVarNW>;
     int chunk, strips, segs, nw, nbp;
     if (!wave_geometry(kernel, kVarNW, P, lam_next, chunk, strips, segs, nw, nbp, 62))
@@ -631,6 +696,13 @@ hipError_t adj2(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& ut, 
 }  // namespace
 
 bool var_wave_fits(const DevGrid& g, int esize) { return g.sz * (int64_t)esize < ((int64_t)1 << 31); }
+
+bool var_pair_wave_fits(const DevGrid& a, const DevGrid& b, const DevGrid& c, const DevGrid& d, int esize) {
+    const DevGrid* g[3] = {&b, &c, &d};
+    for (const DevGrid* x : g)
+        if (x->nx != a.nx || x->ny != a.ny || x->nz != a.nz || x->sy != a.sy || x->sz != a.sz) return false;
+    return var_wave_fits(a, esize);
+}
 
 hipError_t launch_var_forward_wave(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, int dtype, double dt,
                                    hipStream_t s) {

@@ -124,6 +124,9 @@ hipError_t launch_var_adjoint(const DevGrid& lam_next, const DevGrid& lam, const
 // for grids whose planes hold fewer than 2^31 bytes (var_wave_fits); the
 // arithmetic per point is the same chain of fmas as the kernels above.
 bool var_wave_fits(const DevGrid& g, int esize);
+// The fused pair's wave kernel also needs its four inputs (lam'', u_t,
+// u_{t-1}, kappa) laid out alike: one row table addresses them.
+bool var_pair_wave_fits(const DevGrid& a, const DevGrid& b, const DevGrid& c, const DevGrid& d, int esize);
 hipError_t launch_var_forward_wave(const DevGrid& src, const DevGrid& dst, const DevGrid& kappa, int dtype, double dt,
                                    hipStream_t s);
 hipError_t launch_var_adjoint_wave(const DevGrid& lam_next, const DevGrid& lam, const DevGrid& u, const DevGrid& kappa,

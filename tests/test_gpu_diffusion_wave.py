@@ -72,3 +72,34 @@ def test_forward_many_chunks_matches_oracle(dtype):
     out = empty_grid(shape, 1, dtype)
     L.lope_apply_var(ug, out, kg, 0.1, (P, P, P))
     assert rel_err(out.numpy(), oracle.diffusion_step(u, k, 0.1)) <= tol(dtype)
+
+
+@pytest.mark.parametrize("gdt", [np.float64, np.float32])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape", SHAPES + [(70, 6, 130)])
+def test_reverse_pair_edges_and_canaries(shape, dtype, gdt):
+    """Two reverse steps in one pass: lam bitwise equal to two one-step
+    passes, both against the oracle's transposes, halos neither read nor
+    written."""
+    u1, k, lam = _fields(shape, dtype, SHAPES.index(shape) if shape in SHAPES else 40)
+    u0 = np.random.default_rng([synth.CFG_TEST, 950]).uniform(0, 1, shape).astype(dtype)
+    dt = 0.1
+    lg, g1, g0, kg = (grid_from(a, 1, fill=np.nan) for a in (lam, u1, u0, k))
+    out = empty_grid(shape, 1, dtype, fill=np.nan)
+    gk = grid_from(np.full(shape, 0.5, dtype=gdt), 1, fill=np.nan)
+    L.lope_apply_var_adjoint2(lg, out, g1, g0, kg, dt, (P, P, P), gk)
+    for g in (out, gk):
+        assert np.all(np.isnan(g.padded().cpu().numpy()[halo_mask(g)])), "a halo cell was written"
+    got_l, got_g = out.numpy(), gk.numpy() - 0.5
+    assert np.all(np.isfinite(got_l)) and np.all(np.isfinite(got_g)), "the stored (NaN) halo was read"
+    mid = empty_grid(shape, 1, dtype, fill=np.nan)
+    two = empty_grid(shape, 1, dtype, fill=np.nan)
+    acc = grid_from(np.zeros(shape, dtype=gdt), 1)
+    L.lope_apply_var_adjoint(lg, mid, g1, kg, dt, (P, P, P), acc)
+    L.lope_apply_var_adjoint(mid, two, g0, kg, dt, (P, P, P), acc)
+    np.testing.assert_array_equal(got_l, two.numpy())
+    l_t = oracle.diffusion_step_transpose(lam, k, dt)
+    assert rel_err(got_l, oracle.diffusion_step_transpose(l_t, k, dt)) <= tol(dtype)
+    want_g = oracle.diffusion_kappa_vjp(u1, lam, dt) + oracle.diffusion_kappa_vjp(u0, l_t, dt)
+    gtol = tol(gdt if gdt == np.float32 else dtype)
+    assert rel_err(got_g, want_g) <= gtol, rel_err(got_g, want_g)
