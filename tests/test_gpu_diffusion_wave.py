@@ -103,3 +103,23 @@ def test_reverse_pair_edges_and_canaries(shape, dtype, gdt):
     want_g = oracle.diffusion_kappa_vjp(u1, lam, dt) + oracle.diffusion_kappa_vjp(u0, l_t, dt)
     gtol = tol(gdt if gdt == np.float32 else dtype)
     assert rel_err(got_g, want_g) <= gtol, rel_err(got_g, want_g)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_reverse_pair_mixed_layouts(dtype):
+    """Inputs laid out differently (kappa with a wider halo) take the LDS pair
+    kernel (test_gpu_log checks the choice); its results are the wave pair's
+    value for value."""
+    shape = (21, 19, 70)
+    u1, k, lam = _fields(shape, dtype, 60)
+    u0 = np.random.default_rng([synth.CFG_TEST, 951]).uniform(0, 1, shape).astype(dtype)
+    dt = 0.1
+    outs = []
+    for kh in (1, 2):
+        lg, g1, g0, kg = grid_from(lam, 1), grid_from(u1, 1), grid_from(u0, 1), grid_from(k, kh)
+        out = empty_grid(shape, 1, dtype)
+        gk = grid_from(np.zeros(shape, dtype=np.float64), 1)
+        L.lope_apply_var_adjoint2(lg, out, g1, g0, kg, dt, (P, P, P), gk)
+        outs.append((out.numpy(), gk.numpy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
