@@ -179,23 +179,25 @@ struct Cols {
         for (int r = 0; r < NR; ++r) v[r] = bload<T>(rs, xo, row[r]);
     }
     // rows 0 .. NR-1 of plane q (wrapped) into v, the outside columns into e
+    // (live = false: the same loads through a resource of no bytes, which
+    // return 0 and move nothing)
     template <int AUX = 0>
-    __device__ __forceinline__ void load(int q, int nz, T (&v)[NR], T& e) const {
-        const Rsrc rs = plane_rsrc(base + (int64_t)wrap_index(q, nz) * pbytes, pbytes);
+    __device__ __forceinline__ void load(int q, int nz, T (&v)[NR], T& e, bool live = true) const {
+        const Rsrc rs = plane_rsrc(base + (int64_t)wrap_index(q, nz) * pbytes, live ? pbytes : 0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = bload<T, AUX>(rs, xo, row[r]);
         e = bload<T, AUX>(rs, eo, 0);
     }
     // the same for another array of this very layout, based at `other`, plane
     // qw (already wrapped)
-    __device__ __forceinline__ void load_at(const char* other, int qw, T (&v)[NR], T& e) const {
-        const Rsrc rs = plane_rsrc(other + (int64_t)qw * pbytes, pbytes);
+    __device__ __forceinline__ void load_at(const char* other, int qw, T (&v)[NR], T& e, bool live = true) const {
+        const Rsrc rs = plane_rsrc(other + (int64_t)qw * pbytes, live ? pbytes : 0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = bload<T>(rs, xo, row[r]);
         e = bload<T>(rs, eo, 0);
     }
-    __device__ __forceinline__ void load_rows_at(const char* other, int qw, T (&v)[NR]) const {
-        const Rsrc rs = plane_rsrc(other + (int64_t)qw * pbytes, pbytes);
+    __device__ __forceinline__ void load_rows_at(const char* other, int qw, T (&v)[NR], bool live = true) const {
+        const Rsrc rs = plane_rsrc(other + (int64_t)qw * pbytes, live ? pbytes : 0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = bload<T>(rs, xo, row[r]);
     }
@@ -211,11 +213,18 @@ __device__ __forceinline__ void x_neighbours(const T (&v)[NR], T e, T& left, T& 
 }
 
 // PF: planes loaded ahead of the one being computed (1 or 2); LA / SA: cache
-// policy of the loads / stores.
+// policy of the loads / stores.  The planes and their partial sums live in a
+// ring of PF + 2 slots indexed by the step's phase (the march is unrolled by
+// the ring's length), so nothing is copied between registers; every step is
+// the same code, with the loads of planes the march does not need and the
+// stores of planes outside the chunk going through a resource of no bytes
+// (a lane or row without an output through the offset 2^31), which the
+// range check drops: every wait for a plane's loads counts exactly.
 template <typename T, int P, int NW, int PF = 1, int LA = 0, int SA = 0>
 __global__ void __launch_bounds__(NW * 64)
 k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strips, int segs, int nwaves, int nbp) {
-    constexpr int NR = P + 2, NB = PF + 1;
+    constexpr int NR = P + 2, NB = PF + 2;
+    constexpr unsigned kDrop = 0x80000000u;   // past every plane (planes are below 2^31 bytes)
     Brick b;
     if (!brick_of(src, P, chunk, strips, segs, nwaves, nbp, NW, b)) return;
     Cols<T, NR> cu, ck;
@@ -225,67 +234,67 @@ k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strip
     const int nz = src.nz, ny = src.ny;
     const int64_t dpb = dst.sz * (int64_t)sizeof(T);
     const bool xin = b.x0 + lane < src.nx;   // lanes past a ragged x end store nothing
-    const unsigned so = (unsigned)(b.x0 + lane) * (unsigned)sizeof(T);
     const T half = (T)0.5;
+    unsigned vo[P];
+    int sro[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const int y = b.y0 + r;
+        vo[r] = xin && y < ny ? (unsigned)(b.x0 + lane) * (unsigned)sizeof(T) : kDrop;
+        sro[r] = (int)((unsigned)(y < ny ? y : 0) * (unsigned)dst.sy * (unsigned)sizeof(T));
+    }
 
-    T u[NB][NR], k[NB][NR], eu[NB], ek[NB];   // the current plane and PF planes in flight
-    T pu[P], pk[P], acc[P];                   // plane j-1: centre values and its partial sums
+    T u[NB][NR], k[NB][NR], eu[NB], ek[NB];   // planes j - 1, j and PF in flight
+    T acc[NB][P];                             // partial sums of the plane in the same slot
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) u[s][r] = k[s][r] = (T)0;
+#pragma unroll
+        for (int r = 0; r < P; ++r) acc[s][r] = (T)0;
+        eu[s] = ek[s] = (T)0;
+    }
     const int jstart = b.z0 - 1, jend = b.zend;
     static_for<0, PF>([&](auto q) __attribute__((always_inline)) {
         constexpr int Q = decltype(q)::value;
-        if (jstart + Q <= jend) {
-            cu.template load<LA>(jstart + Q, nz, u[Q], eu[Q]);
-            ck.template load<LA>(jstart + Q, nz, k[Q], ek[Q]);
-        }
+        cu.template load<LA>(jstart + Q, nz, u[Q], eu[Q], jstart + Q <= jend);
+        ck.template load<LA>(jstart + Q, nz, k[Q], ek[Q], jstart + Q <= jend);
     });
 
-    // march step j with plane j in buffer C
+    // march step j with plane j in slot C, j - 1 in slot PV
     auto step = [&](int j, auto cur_c) __attribute__((always_inline)) {
-        constexpr int C = decltype(cur_c)::value, N = (C + PF) % NB;
-        if (j + PF <= jend) {
-            cu.template load<LA>(j + PF, nz, u[N], eu[N]);
-            ck.template load<LA>(j + PF, nz, k[N], ek[N]);
-        }
+        constexpr int C = decltype(cur_c)::value, PV = (C + NB - 1) % NB, N = (C + PF) % NB;
+        cu.template load<LA>(j + PF, nz, u[N], eu[N], j + PF <= jend);
+        ck.template load<LA>(j + PF, nz, k[N], ek[N], j + PF <= jend);
         const T(&U)[NR] = u[C];
         const T(&K)[NR] = k[C];
+        const T(&pU)[NR] = u[PV];
+        const T(&pK)[NR] = k[PV];
+        // plane j's in-plane terms
         T a[P];
-        const bool own = j >= b.z0 && j < b.zend;   // plane j is one of the brick's outputs
-        if (own) {   // its in-plane terms
-            static_for<1, P + 1>([&](auto rc) __attribute__((always_inline)) {
-                constexpr int r = decltype(rc)::value;
-                const T uc = U[r], kc = K[r];
-                T ul, ur, kl, kr;
-                x_neighbours<r>(U, eu[C], ul, ur);
-                x_neighbours<r>(K, ek[C], kl, kr);
-                T s = (T)0;
-                s = fma(half * (kc + kl), ul - uc, s);
-                s = fma(half * (kc + kr), ur - uc, s);
-                s = fma(half * (kc + K[r - 1]), U[r - 1] - uc, s);
-                s = fma(half * (kc + K[r + 1]), U[r + 1] - uc, s);
-                a[r - 1] = s;
-            });
-        }
-        if (j > jstart) {
-            // the face between planes j-1 and j: plane j's z- term, and plane
-            // j-1's z+ term, which completes it
-            const bool done = j - 1 >= b.z0;
-            const Rsrc rd = plane_rsrc((const char*)dst.origin + (int64_t)(j - 1) * dpb, dpb);
-#pragma unroll
-            for (int r = 0; r < P; ++r) {
-                const T w = half * (pk[r] + K[r + 1]);
-                const T d = U[r + 1] - pu[r];
-                const int y = b.y0 + r;
-                if (done && y < ny && xin)
-                    bstore<SA>(fma(dt, fma(w, d, acc[r]), pu[r]), rd, so,
-                               (int)((unsigned)y * (unsigned)dst.sy * (unsigned)sizeof(T)));
-                if (own) a[r] = fma(w, -d, a[r]);
-            }
-        }
+        static_for<1, P + 1>([&](auto rc) __attribute__((always_inline)) {
+            constexpr int r = decltype(rc)::value;
+            const T uc = U[r], kc = K[r];
+            T ul, ur, kl, kr;
+            x_neighbours<r>(U, eu[C], ul, ur);
+            x_neighbours<r>(K, ek[C], kl, kr);
+            T s = (T)0;
+            s = fma(half * (kc + kl), ul - uc, s);
+            s = fma(half * (kc + kr), ur - uc, s);
+            s = fma(half * (kc + K[r - 1]), U[r - 1] - uc, s);
+            s = fma(half * (kc + K[r + 1]), U[r + 1] - uc, s);
+            a[r - 1] = s;
+        });
+        // the face between planes j-1 and j: plane j's z- term, and plane j-1's
+        // z+ term, which completes it
+        const bool done = j - 1 >= b.z0 && j - 1 < b.zend;
+        const Rsrc rd = plane_rsrc((const char*)dst.origin + (int64_t)(done ? j - 1 : b.z0) * dpb, done ? dpb : 0);
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            pu[r] = U[r + 1];
-            pk[r] = K[r + 1];
-            acc[r] = own ? a[r] : (T)0;
+            const T w = half * (pK[r + 1] + K[r + 1]);
+            const T d = U[r + 1] - pU[r + 1];
+            bstore<SA>(fma(dt, fma(w, d, acc[PV][r]), pU[r + 1]), rd, vo[r], sro[r]);
+            acc[C][r] = fma(w, -d, a[r]);
         }
     };
     int j = jstart;
@@ -506,10 +515,12 @@ k_varw_adjoint2(DevGrid lnext, DevGrid lam, DevGrid ut, DevGrid utm1, DevGrid ka
         constexpr int C = decltype(phase)::value, PV = (C + 2) % 3, NX = (C + 1) % 3;
         const int m = q - 1;
         const int qw = plane_wrap(q, nz), qn = qw + 1 < nz ? qw + 1 : 0;
-        c.load_at(bl, qn, l[NX], el[NX]);
-        c.load_at(bu, qn, u[NX], eu[NX]);
-        c.load_at(bk, qn, k[NX], ek[NX]);
-        c.load_rows_at(bv, qw, v[C]);
+        // (planes past the march's end are loaded through a resource of no
+        // bytes: the same instructions, no traffic)
+        c.load_at(bl, qn, l[NX], el[NX], q + 1 <= qend);
+        c.load_at(bu, qn, u[NX], eu[NX], q + 1 <= qend);
+        c.load_at(bk, qn, k[NX], ek[NX], q + 1 <= qend);
+        c.load_rows_at(bv, qw, v[C], q <= zend);
         {
             // the old gradient of plane m (added when m is completed, next step)
             const bool own2 = m >= z0 && m < zend;
