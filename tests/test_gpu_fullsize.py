@@ -60,6 +60,27 @@ def test_heat3d_512_f32_sampled_and_properties():
     assert float(out.min()) >= float(u.min()) - 1e-6 and float(out.max()) <= float(u.max()) + 1e-6
 
 
+def test_heat3d_512_f32_dirichlet_sampled_and_bitwise():
+    """The 512^3 heat grid under a Dirichlet rule on every axis, with the tuned
+    default (the wave brick, 4 sweeps per pass, blends only in the bricks on
+    the interior's edge): sampled outputs (corners and faces included) against
+    the oracle, and the 8-sweep state bitwise equal to one sweep per pass; the
+    1000-sweep run stays within [min(u0, 0), max(u0, 0)] (weights >= 0 summing
+    to one, g = 0)."""
+    case = synth.case_heat3d(n=512, dtype=np.float32, steps=1000)
+    bc = synth.Boundary((D, D, D), 0.0)
+    u = case.field
+    for n in (4, 8):
+        got, want = _sampled(u, case.stencil, bc, n, 0, seed=20 + n)
+        assert rel_err(got, want) <= 1e-5, (n, rel_err(got, want))
+    fused = _run(u, case.stencil, bc, 8).interior().cpu().numpy()
+    plain = _run(u, case.stencil, bc, 8, tdepth=1).interior().cpu().numpy()
+    np.testing.assert_array_equal(fused, plain)
+    out = _run(u, case.stencil, bc, case.steps).interior()
+    lo, hi = min(float(u.min()), 0.0), max(float(u.max()), 0.0)
+    assert float(out.min()) >= lo - 1e-6 and float(out.max()) <= hi + 1e-6
+
+
 def test_heat3d_512_f32_fused_kernels_bitwise():
     """At the full size every fused 3D radius-1 float32 kernel (each wave-brick
     variant and the automatic choice) gives the values of one sweep per pass,
