@@ -59,7 +59,7 @@ typedef enum lope_status {
                                      pointer not device memory, or storage outside its allocation */
     LOPE_ERR_HALO_TOO_SMALL = -2, /* stencil reaches beyond the halo on some side (section 3.5) */
     LOPE_ERR_ALIAS = -3,          /* source and destination interiors overlap (section 2.2, 3.5) */
-    LOPE_ERR_UNSUPPORTED = -4,    /* valid request this build does not implement (see each call) */
+    LOPE_ERR_UNSUPPORTED = -4,    /* valid request the library does not implement (see each call) */
     LOPE_ERR_NO_DEVICE = -5,      /* no usable GPU (or LOPE_FORCE_NO_DEVICE=1 in the environment) */
     LOPE_ERR_HIP = -6             /* a HIP runtime error; its text is in lope_last_error() */
 } lope_status;

@@ -155,7 +155,7 @@ def load_cache_file(path):
 
 
 def register_cache(path=None) -> int:
-    """Register every cached choice whose variant exists in this build; returns the count."""
+    """Register every cached choice whose variant the compiled library has; returns the count."""
     path = path or os.environ.get("LOPE_TUNE_CACHE", DEFAULT_CACHE)
     cache = load_cache_file(path)
     if not cache:
