@@ -305,11 +305,15 @@ k_varw_forward(DevGrid src, DevGrid dst, DevGrid kap, T dt, int chunk, int strip
     });
 }
 
+// The one-step reverse in the same form as the forward step: planes, partial
+// sums and the old gradient in a ring of PF + 2 slots, every step the same
+// loads and stores (out-of-chunk ones through resources of no bytes).
 template <typename T, typename TG, int P, int NW, int PF = 1, int SA = 0>
 __global__ void __launch_bounds__(NW * 64)
 k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, T dt, int chunk, int strips, int segs,
                int nwaves, int nbp) {
-    constexpr int NR = P + 2, NB = PF + 1;
+    constexpr int NR = P + 2, NB = PF + 2;
+    constexpr unsigned kDrop = 0x80000000u;   // past every plane (planes are below 2^31 bytes)
     Brick b;
     if (!brick_of(lnext, P, chunk, strips, segs, nwaves, nbp, NW, b)) return;
     Cols<T, NR> cl, cu, ck;
@@ -319,97 +323,97 @@ k_varw_adjoint(DevGrid lnext, DevGrid lam, DevGrid ug, DevGrid kap, DevGrid gk, 
     const int lane = threadIdx.x & 63;
     const int nz = lnext.nz, ny = lnext.ny;
     const bool xin = b.x0 + lane < lnext.nx;   // lanes past a ragged x end store nothing
-    const unsigned so = (unsigned)(b.x0 + lane) * (unsigned)sizeof(T);
-    const unsigned sg = (unsigned)(b.x0 + lane) * (unsigned)sizeof(TG);
     const int64_t lpb = lam.sz * (int64_t)sizeof(T), gpb = gk.sz * (int64_t)sizeof(TG);
     const T half = (T)0.5, hdt = (T)0.5 * dt;
+    unsigned vol[P], vog[P];
+    int srl[P], srg[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const int y = b.y0 + r;
+        const bool ok = xin && y < ny;
+        vol[r] = ok ? (unsigned)(b.x0 + lane) * (unsigned)sizeof(T) : kDrop;
+        vog[r] = ok ? (unsigned)(b.x0 + lane) * (unsigned)sizeof(TG) : kDrop;
+        const int yr = y < ny ? y : 0;
+        srl[r] = (int)((unsigned)yr * (unsigned)lam.sy * (unsigned)sizeof(T));
+        srg[r] = (int)((unsigned)yr * (unsigned)gk.sy * (unsigned)sizeof(TG));
+    }
 
-    T l[NB][NR], u[NB][NR], k[NB][NR], el[NB], eu[NB], ek[NB];
-    T pl[P], pu[P], pk[P], al[P], ag[P];
-    TG gold[P];   // kappa gradient of plane j-1, read one step ahead
+    T l[NB][NR], u[NB][NR], k[NB][NR], el[NB], eu[NB], ek[NB];   // planes j - 1, j, PF in flight
+    T al[NB][P], ag[NB][P];   // partial sums (lam, gradient) of the plane in the same slot
+    TG gold[NB][P];           // kappa gradient of the plane in the same slot, read one step ahead
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) l[s][r] = u[s][r] = k[s][r] = (T)0;
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            al[s][r] = ag[s][r] = (T)0;
+            gold[s][r] = (TG)0;
+        }
+        el[s] = eu[s] = ek[s] = (T)0;
+    }
     const int jstart = b.z0 - 1, jend = b.zend;
     static_for<0, PF>([&](auto q) __attribute__((always_inline)) {
         constexpr int Q = decltype(q)::value;
-        if (jstart + Q <= jend) {
-            cl.load(jstart + Q, nz, l[Q], el[Q]);
-            cu.load(jstart + Q, nz, u[Q], eu[Q]);
-            ck.load(jstart + Q, nz, k[Q], ek[Q]);
-        }
+        cl.load(jstart + Q, nz, l[Q], el[Q], jstart + Q <= jend);
+        cu.load(jstart + Q, nz, u[Q], eu[Q], jstart + Q <= jend);
+        ck.load(jstart + Q, nz, k[Q], ek[Q], jstart + Q <= jend);
     });
-#pragma unroll
-    for (int r = 0; r < P; ++r) gold[r] = (TG)0;
 
     auto step = [&](int j, auto cur_c) __attribute__((always_inline)) {
-        constexpr int C = decltype(cur_c)::value, N = (C + PF) % NB;
-        if (j + PF <= jend) {
-            cl.load(j + PF, nz, l[N], el[N]);
-            cu.load(j + PF, nz, u[N], eu[N]);
-            ck.load(j + PF, nz, k[N], ek[N]);
-        }
+        constexpr int C = decltype(cur_c)::value, PV = (C + NB - 1) % NB, N = (C + PF) % NB;
+        cl.load(j + PF, nz, l[N], el[N], j + PF <= jend);
+        cu.load(j + PF, nz, u[N], eu[N], j + PF <= jend);
+        ck.load(j + PF, nz, k[N], ek[N], j + PF <= jend);
         const T(&L)[NR] = l[C];
         const T(&U)[NR] = u[C];
         const T(&K)[NR] = k[C];
-        T a[P], g[P];
-        TG gnew[P];
-        const bool own = j >= b.z0 && j < b.zend;   // plane j is one of the brick's outputs
-        if (own) {
-            // its kappa gradient (read now, updated when the plane completes)
-            // and its in-plane terms
-            const Rsrc rgj = plane_rsrc((const char*)gk.origin + (int64_t)j * gpb, gpb);
-            static_for<1, P + 1>([&](auto rc) __attribute__((always_inline)) {
-                constexpr int r = decltype(rc)::value;
-                const int y = b.y0 + r - 1;
-                gnew[r - 1] = y < ny && xin ? bload<TG>(rgj, sg, (int)((unsigned)y * (unsigned)gk.sy * (unsigned)sizeof(TG))) : (TG)0;
-                const T lc = L[r], uc = U[r], kc = K[r];
-                T ll, lr, ul, ur, kl, kr;
-                x_neighbours<r>(L, el[C], ll, lr);
-                x_neighbours<r>(U, eu[C], ul, ur);
-                x_neighbours<r>(K, ek[C], kl, kr);
-                T s = (T)0, t = (T)0;
-                s = fma(half * (kc + kl), ll - lc, s);
-                t = fma(ul - uc, lc - ll, t);
-                s = fma(half * (kc + kr), lr - lc, s);
-                t = fma(ur - uc, lc - lr, t);
-                s = fma(half * (kc + K[r - 1]), L[r - 1] - lc, s);
-                t = fma(U[r - 1] - uc, lc - L[r - 1], t);
-                s = fma(half * (kc + K[r + 1]), L[r + 1] - lc, s);
-                t = fma(U[r + 1] - uc, lc - L[r + 1], t);
-                a[r - 1] = s;
-                g[r - 1] = t;
-            });
-        }
-        if (j > jstart) {
-            // the face between planes j-1 and j (both sides' terms are the same
-            // products with opposite signs); plane j-1 completes
-            const bool done = j - 1 >= b.z0;
-            const Rsrc rl = plane_rsrc((const char*)lam.origin + (int64_t)(j - 1) * lpb, lpb);
-            const Rsrc rg = plane_rsrc((const char*)gk.origin + (int64_t)(j - 1) * gpb, gpb);
+        const T(&pL)[NR] = l[PV];
+        const T(&pU)[NR] = u[PV];
+        const T(&pK)[NR] = k[PV];
+        // plane j's kappa gradient (read now, updated when the plane completes)
+        {
+            const bool own = j >= b.z0 && j < b.zend;
+            const Rsrc rgj = plane_rsrc((const char*)gk.origin + (int64_t)(own ? j : b.z0) * gpb, own ? gpb : 0);
 #pragma unroll
-            for (int r = 0; r < P; ++r) {
-                const T w = half * (pk[r] + K[r + 1]);
-                const T dl = L[r + 1] - pl[r];   // lam'_j - lam'_{j-1}
-                const T du = U[r + 1] - pu[r];   // u_j - u_{j-1}
-                const int y = b.y0 + r;
-                if (done && y < ny && xin) {
-                    bstore<SA>(fma(dt, fma(w, dl, al[r]), pl[r]), rl, so,
-                               (int)((unsigned)y * (unsigned)lam.sy * (unsigned)sizeof(T)));
-                    bstore<SA>(gold[r] + (TG)(hdt * fma(du, -dl, ag[r])), rg, sg,
-                               (int)((unsigned)y * (unsigned)gk.sy * (unsigned)sizeof(TG)));
-                }
-                if (own) {
-                    a[r] = fma(w, -dl, a[r]);
-                    g[r] = fma(-du, dl, g[r]);
-                }
-            }
+            for (int r = 0; r < P; ++r) gold[C][r] = bload<TG>(rgj, vog[r], srg[r]);
         }
+        // plane j's in-plane terms
+        T a[P], g[P];
+        static_for<1, P + 1>([&](auto rc) __attribute__((always_inline)) {
+            constexpr int r = decltype(rc)::value;
+            const T lc = L[r], uc = U[r], kc = K[r];
+            T ll, lr, ul, ur, kl, kr;
+            x_neighbours<r>(L, el[C], ll, lr);
+            x_neighbours<r>(U, eu[C], ul, ur);
+            x_neighbours<r>(K, ek[C], kl, kr);
+            T s = (T)0, t = (T)0;
+            s = fma(half * (kc + kl), ll - lc, s);
+            t = fma(ul - uc, lc - ll, t);
+            s = fma(half * (kc + kr), lr - lc, s);
+            t = fma(ur - uc, lc - lr, t);
+            s = fma(half * (kc + K[r - 1]), L[r - 1] - lc, s);
+            t = fma(U[r - 1] - uc, lc - L[r - 1], t);
+            s = fma(half * (kc + K[r + 1]), L[r + 1] - lc, s);
+            t = fma(U[r + 1] - uc, lc - L[r + 1], t);
+            a[r - 1] = s;
+            g[r - 1] = t;
+        });
+        // the face between planes j-1 and j (both sides' terms are the same
+        // products with opposite signs); plane j-1 completes
+        const bool done = j - 1 >= b.z0 && j - 1 < b.zend;
+        const int pc = done ? j - 1 : b.z0;
+        const Rsrc rl = plane_rsrc((const char*)lam.origin + (int64_t)pc * lpb, done ? lpb : 0);
+        const Rsrc rg = plane_rsrc((const char*)gk.origin + (int64_t)pc * gpb, done ? gpb : 0);
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            pl[r] = L[r + 1];
-            pu[r] = U[r + 1];
-            pk[r] = K[r + 1];
-            al[r] = own ? a[r] : (T)0;
-            ag[r] = own ? g[r] : (T)0;
-            gold[r] = own ? gnew[r] : (TG)0;
+            const T w = half * (pK[r + 1] + K[r + 1]);
+            const T dl = L[r + 1] - pL[r + 1];   // lam'_j - lam'_{j-1}
+            const T du = U[r + 1] - pU[r + 1];   // u_j - u_{j-1}
+            bstore<SA>(fma(dt, fma(w, dl, al[PV][r]), pL[r + 1]), rl, vol[r], srl[r]);
+            bstore<SA>(gold[PV][r] + (TG)(hdt * fma(du, -dl, ag[PV][r])), rg, vog[r], srg[r]);
+            al[C][r] = fma(w, -dl, a[r]);
+            ag[C][r] = fma(-du, dl, g[r]);
         }
     };
     int j = jstart;
