@@ -204,6 +204,24 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
 #pragma unroll
     for (int r = 0; r < NR; ++r) prev[r] = (T)0;
     const unsigned dsyb = (unsigned)dst.sy * (unsigned)sizeof(T);
+    // The outputs of a completed plane are stored in the next step, after its
+    // first level (whose start waits for that step's plane): stored at the
+    // end of their own step they would be waited for at once by the next
+    // step's wait for its loads; stored one level later they have most of a
+    // step to complete before that wait.
+    T pend[P];
+    int pend_p = -1;   // plane of the values in pend (-1: nothing to store)
+#pragma unroll
+    for (int i = 0; i < P; ++i) pend[i] = (T)0;
+    auto store_pending = [&]() __attribute__((always_inline)) {
+        if (pend_p >= 0 && keep) {
+            const __amdgpu_buffer_rsrc_t rd = plane_rsrc(dp + pend_p * dszb, dszb);
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                if (y0 + i < yend) buffer_store(pend[i], rd, (unsigned)(y0 + i) * dsyb + xoff);
+        }
+        pend_p = -1;
+    };
     // March step j (phase u = (j - jstart) mod 3 of the three-step unroll):
     // level 0 is the plane in pf[u % PF]; once consumed, that buffer takes the
     // plane PF steps ahead (past the end: a repeat of the last plane, never
@@ -259,7 +277,10 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
                 // alpha * (that plane of level k-1), completed this step
                 nw[r] = with_alpha ? fma(c.c[0], bl[r], alpha * base[r]) : c.c[0] * bl[r];
             }
-            if (k == 0) load_plane(min(j + PF, jend), pf[u % PF], zrule);
+            if (k == 0) {
+                if (KM == TD) store_pending();
+                load_plane(min(j + PF, jend), pf[u % PF], zrule);
+            }
             // the rule on the completed plane p of level k+1
             const int p = j - k - 1;
             const bool gz = ZR && (p < 0 || p >= nz);
@@ -272,15 +293,14 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
             if (k + 1 < TD) {
 #pragma unroll
                 for (int r = k + 1; r < NR - 1 - k; ++r) cur[r] = nxt[r];
-            } else if (p >= z0 && p < zend && keep) {
-                const __amdgpu_buffer_rsrc_t rd = plane_rsrc(dp + p * dszb, dszb);
+            } else if (p >= z0 && p < zend) {
 #pragma unroll
-                for (int r = TD; r < NR - TD; ++r) {
-                    const int y = y0 + (r - TD);
-                    if (y < yend) {
-                        buffer_store(nxt[r], rd, (unsigned)y * dsyb + xoff);
-                        if (RES) rmax = nan_max(rmax, fabs((double)nxt[r] - (double)prev[r]));
-                    }
+                for (int r = TD; r < NR - TD; ++r) pend[r - TD] = nxt[r];
+                pend_p = p;
+                if (RES && keep) {
+#pragma unroll
+                    for (int r = TD; r < NR - TD; ++r)
+                        if (y0 + (r - TD) < yend) rmax = nan_max(rmax, fabs((double)nxt[r] - (double)prev[r]));
                 }
             }
             // RES: level TD-1's plane p + 1 is the state before the last sweep
@@ -331,6 +351,7 @@ __device__ __forceinline__ void wave_brick(const DevGrid& src, const DevGrid& ds
         if (j + 2 > jend) break;
         step(j + 2, ph2, all, zr);
     }
+    store_pending();
     if (RES) residual_merge(rmax, residual);
 }
 
