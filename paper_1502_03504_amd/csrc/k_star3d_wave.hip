@@ -479,7 +479,6 @@ const Variant kStar3dWave[] = {
     WSTAR(float, LOPE_F32, 4, 8, 4, 1, 2, 0),
     WSTAR(float, LOPE_F32, 4, 10, 4, 1, 2, 0),
     WSTAR(float, LOPE_F32, 4, 6, 4, 1, 2, 0),
-    WSTAR(float, LOPE_F32, 4, 8, 4, 3, 2, 0),
 };
 
 }  // namespace
