@@ -61,7 +61,8 @@ typedef enum lope_status {
     LOPE_ERR_ALIAS = -3,          /* source and destination interiors overlap (section 2.2, 3.5) */
     LOPE_ERR_UNSUPPORTED = -4,    /* valid request the library does not implement (see each call) */
     LOPE_ERR_NO_DEVICE = -5,      /* no usable GPU (or LOPE_FORCE_NO_DEVICE=1 in the environment) */
-    LOPE_ERR_HIP = -6             /* a HIP runtime error; its text is in lope_last_error() */
+    LOPE_ERR_HIP = -6,            /* a HIP runtime error; its text is in lope_last_error() */
+    LOPE_ERR_TIMEOUT = -7         /* a bounded device-side wait ran out (lope_batch_persistent_check) */
 } lope_status;
 
 /* Device id returned by lope_get_device when no device can be used. */
@@ -348,6 +349,30 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
  * launches are enqueued directly into the caller's graph instead.
  * lope_batch_result_index tells which buffer holds the result. */
 int lope_batch_apply(lope_batch_plan* plan, void* stream);
+
+/* The same passes as lope_batch_apply in ONE kernel launch (the persistent
+ * batched sweep; the sweep and the double buffering of sections 3.2-3.3 for
+ * every grid): the kernel's waves take work units, one strip of one grid in
+ * one pass each, from a queue numbered pass by pass, and a unit starts once
+ * every strip of its grid's earlier passes is complete (per-grid counters,
+ * agent-scope release and acquire).  A wave waits only on units handed out
+ * before its own, so the queue cannot deadlock whatever the number of
+ * resident waves; every wait is also bounded (1 s, or the environment's
+ * LOPE_PERSISTENT_WAIT_US microseconds, read at each call; 0 makes any wait
+ * not met at once run out), and one that runs out makes all waves leave early
+ * (see lope_batch_persistent_check).  The result
+ * equals lope_batch_apply's value for value, in the buffer
+ * lope_batch_result_index names, with the plan's tiling.  Enqueued on
+ * `stream` with no other operation, so a caller may capture it into a graph
+ * as one kernel node; the kernel's last wave clears the plan's queue for the
+ * next launch.  Launches of one plan must not overlap (they share its queue):
+ * keep them on one stream.  Errors: LOPE_ERR_INVALID_ARG (null plan). */
+int lope_batch_apply_persistent(lope_batch_plan* plan, void* stream);
+
+/* Synchronises the device, then returns LOPE_ERR_TIMEOUT if a wait of an
+ * earlier lope_batch_apply_persistent of this plan ran out of time (that
+ * launch's result is invalid; the record is cleared), else LOPE_OK. */
+int lope_batch_persistent_check(lope_batch_plan* plan);
 
 /* Same work as lope_batch_apply as ordinary lope_iterate launches, one per
  * grid per sweep (the baseline the batched launch is compared with). */

@@ -14,6 +14,7 @@ LOPE_ERR_ALIAS = -3
 LOPE_ERR_UNSUPPORTED = -4
 LOPE_ERR_NO_DEVICE = -5
 LOPE_ERR_HIP = -6
+LOPE_ERR_TIMEOUT = -7
 LOPE_HOST = -1
 
 LOPE_F32 = 0
@@ -116,6 +117,8 @@ SIGNATURES = {
                                               P(c_void_p)]),
     "lope_batch_apply": (ctypes.c_int, [c_void_p, c_void_p]),
     "lope_batch_apply_per_grid": (ctypes.c_int, [c_void_p, c_void_p]),
+    "lope_batch_apply_persistent": (ctypes.c_int, [c_void_p, c_void_p]),
+    "lope_batch_persistent_check": (ctypes.c_int, [c_void_p]),
     "lope_batch_plan_set_depth": (ctypes.c_int, [c_void_p, ctypes.c_int32]),
     "lope_batch_plan_set_tiles": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "lope_batch_plan_get_tiles": (ctypes.c_int, [c_void_p, P(ctypes.c_int32), P(ctypes.c_int32)]),

@@ -1,4 +1,5 @@
-"""Batch plans: many uneven 2D grids swept together, one launch per fused pass."""
+"""Batch plans: many uneven 2D grids swept together, one launch per fused pass
+(or every pass in one persistent launch)."""
 from __future__ import annotations
 
 import ctypes
@@ -39,6 +40,14 @@ class BatchPlan:
 
     def apply_per_grid(self, stream=None) -> None:
         check(load().lope_batch_apply_per_grid(self.handle, self._stream(stream)))
+
+    def apply_persistent(self, stream=None) -> None:
+        """The passes of ``apply`` in one persistent kernel launch (same result)."""
+        check(load().lope_batch_apply_persistent(self.handle, self._stream(stream)))
+
+    def check_persistent(self) -> None:
+        """Synchronise; raise if a wait of an earlier persistent launch ran out."""
+        check(load().lope_batch_persistent_check(self.handle))
 
     def set_depth(self, tdepth: int) -> None:
         """Sweeps fused per launch (1..8)."""
@@ -114,6 +123,14 @@ def lope_batch_apply(plan: BatchPlan, stream=None) -> None:
 
 def lope_batch_apply_per_grid(plan: BatchPlan, stream=None) -> None:
     plan.apply_per_grid(stream)
+
+
+def lope_batch_apply_persistent(plan: BatchPlan, stream=None) -> None:
+    plan.apply_persistent(stream)
+
+
+def lope_batch_persistent_check(plan: BatchPlan) -> None:
+    plan.check_persistent()
 
 
 def lope_batch_plan_destroy(plan: BatchPlan) -> None:

@@ -778,6 +778,11 @@ struct lope_batch_plan {
     int items_rows[kBatchMaxDepth + 1] = {};   // rows per strip each table was built with
     hipGraphExec_t graph = nullptr;   // every pass of lope_batch_apply, recorded for (graph_depth, graph_rows)
     int graph_depth = 0, graph_rows = 0;
+    // persistent launch: queue state followed by one PqGrid per grid (zeroed at
+    // creation); the strip counts are those of the tiling (pq_depth, pq_rows)
+    PqState* d_pq = nullptr;
+    PqGrid* d_pqg = nullptr;
+    int pq_depth = 0, pq_rows = 0;
 };
 
 namespace {
@@ -786,6 +791,7 @@ void plan_free(lope_batch_plan* p) {
     if (!p) return;
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
     if (p->d_grids) (void)hipFree(p->d_grids);
+    if (p->d_pq) (void)hipFree(p->d_pq);
     for (int d = 0; d <= kBatchMaxDepth; ++d)
         if (p->d_items[d]) (void)hipFree(p->d_items[d]);
     delete p;
@@ -817,6 +823,49 @@ int plan_items(lope_batch_plan* p, int depth) {
         p->nitems[depth] = 0;
         return hip_fail(e, "batch tile table upload");
     }
+    return LOPE_OK;
+}
+
+// Queue state of the persistent launch for the plan's tiling: allocated and
+// zeroed once, and each grid's strip count in the full-depth table uploaded
+// whenever the tiling changes (after the device is idle, since a running
+// launch reads them).
+int plan_pq(lope_batch_plan* p) {
+    if (p->d_pq && p->pq_depth == p->tdepth && p->pq_rows == p->rows) return LOPE_OK;
+    const size_t n = p->grids.size();
+    hipError_t e = hipSuccess;
+    if (!p->d_pq) {
+        const size_t bytes = sizeof(PqState) + std::max<size_t>(n, 1) * sizeof(PqGrid);
+        e = hipMalloc(&p->d_pq, bytes);
+        if (e == hipSuccess) e = hipMemset(p->d_pq, 0, bytes);
+        if (e != hipSuccess) {
+            if (p->d_pq) (void)hipFree(p->d_pq);
+            p->d_pq = nullptr;
+            return hip_fail(e, "persistent batch state");
+        }
+        p->d_pqg = reinterpret_cast<PqGrid*>(p->d_pq + 1);
+    } else if ((e = hipDeviceSynchronize()) != hipSuccess) {
+        return hip_fail(e, "device synchronisation before the persistent batch tables");
+    }
+    const int64_t bw = batch_strip_width(p->tdepth), full = p->n_steps / p->tdepth;
+    const int rem = (int)(p->n_steps % p->tdepth);
+    const int64_t bwr = rem ? batch_strip_width(rem) : 1;
+    std::vector<PqGrid> hg(std::max<size_t>(n, 1));
+    for (size_t i = 0; i < n; ++i) {
+        const int64_t nx = p->items[i].src.n[0], ny = p->items[i].src.n[1];
+        const int64_t ry = (ny + p->rows - 1) / p->rows;
+        const int64_t fs = (nx && ny) ? ry * ((nx + bw - 1) / bw) : 0;
+        const int64_t rs = (nx && ny && rem) ? ry * ((nx + bwr - 1) / bwr) : 0;
+        // the per-grid counter reaches full * fs + rs in one launch
+        if (full * fs + rs > (int64_t)INT32_MAX)
+            return fail(LOPE_ERR_UNSUPPORTED, "grid %zu has too many strips for one persistent launch", i);
+        hg[i].done = 0;
+        hg[i].full_strips = (int32_t)fs;
+    }
+    e = hipMemcpy(p->d_pqg, hg.data(), n * sizeof(PqGrid), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "persistent batch table upload");
+    p->pq_depth = p->tdepth;
+    p->pq_rows = p->rows;
     return LOPE_OK;
 }
 
@@ -1343,7 +1392,8 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         plan_free(p);
         return hip_fail(e, "batch plan upload");
     }
-    if ((rc = plan_items(p, p->tdepth)) || (n_steps % p->tdepth && (rc = plan_items(p, (int)(n_steps % p->tdepth))))) {
+    if ((rc = plan_items(p, p->tdepth)) || (n_steps % p->tdepth && (rc = plan_items(p, (int)(n_steps % p->tdepth)))) ||
+        (rc = plan_pq(p))) {
         plan_free(p);
         return rc;
     }
@@ -1363,7 +1413,7 @@ int lope_batch_plan_set_tiles(lope_batch_plan* plan, int32_t tdepth, int32_t row
     plan->tdepth = tdepth;
     if (rows > 0) plan->rows = rows;
     if ((rc = plan_items(plan, tdepth)) ||
-        (plan->n_steps % tdepth && (rc = plan_items(plan, (int)(plan->n_steps % tdepth))))) {
+        (plan->n_steps % tdepth && (rc = plan_items(plan, (int)(plan->n_steps % tdepth)))) || (rc = plan_pq(plan))) {
         plan->tdepth = old_depth;
         plan->rows = old_rows;
         return rc;
@@ -1428,6 +1478,58 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream) {
     }
     e = hipGraphLaunch(plan->graph, s);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "batch graph launch");
+}
+
+int lope_batch_apply_persistent(lope_batch_plan* plan, void* stream) {
+    if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
+    int rc;
+    if ((rc = device_ready())) return rc;
+    if (plan_passes(plan) == 0) return LOPE_OK;
+    if (!plan->d_pq || plan->pq_depth != plan->tdepth || plan->pq_rows != plan->rows)
+        return fail(LOPE_ERR_INVALID_ARG, "persistent batch state does not match the plan's tiling");
+    const int rem = (int)(plan->n_steps % plan->tdepth);
+    PqShape shape;
+    shape.n_full = plan->nitems[plan->tdepth];
+    shape.n_rem = rem ? plan->nitems[rem] : 0;
+    shape.full = (int32_t)(plan->n_steps / plan->tdepth);
+    log_line("batch of %zu grids, %lld sweeps: one persistent launch, %d per pass, %d-row strips, %lld passes, "
+             "%lld units",
+             plan->grids.size(), (long long)plan->n_steps, plan->tdepth, plan->rows, (long long)plan_passes(plan),
+             (long long)pq_total(shape));
+    // time limit of one dependency wait: 1 s, or LOPE_PERSISTENT_WAIT_US
+    // microseconds (read at each launch; 0 makes any wait not met at once run
+    // out, which exercises the abort path)
+    long long wait_us = 1000000;
+    if (const char* w = getenv("LOPE_PERSISTENT_WAIT_US")) {
+        char* end = nullptr;
+        const long long v = strtoll(w, &end, 10);
+        if (end == w || *end != '\0' || v < 0 || v > 1000000000ll)
+            return fail(LOPE_ERR_INVALID_ARG, "LOPE_PERSISTENT_WAIT_US=%s is not 0..1000000000", w);
+        wait_us = v;
+    }
+    const hipError_t e = launch_batch_persistent(plan->d_grids, plan->d_items[plan->tdepth],
+                                                 rem ? plan->d_items[rem] : nullptr, shape, plan->tdepth, rem,
+                                                 plan->d_pq, plan->d_pqg, (int)plan->grids.size(), wait_us,
+                                                 plan->dtype, (hipStream_t)stream);
+    return e == hipSuccess ? LOPE_OK : hip_fail(e, "persistent batch launch");
+}
+
+int lope_batch_persistent_check(lope_batch_plan* plan) {
+    if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
+    int rc;
+    if ((rc = device_ready())) return rc;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "device synchronisation");
+    if (!plan->d_pq) return LOPE_OK;
+    unsigned int timeouts = 0;
+    e = hipMemcpy(&timeouts, &plan->d_pq->timeouts, sizeof(timeouts), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "persistent batch status");
+    if (timeouts == 0) return LOPE_OK;
+    const unsigned int zero = 0;
+    e = hipMemcpy(&plan->d_pq->timeouts, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "persistent batch status reset");
+    return fail(LOPE_ERR_TIMEOUT, "%u wait(s) of a persistent batch launch ran out of time; its result is invalid",
+                timeouts);
 }
 
 int lope_batch_apply_per_grid(lope_batch_plan* plan, void* stream) {
@@ -1547,6 +1649,7 @@ const char* lope_status_string(int status) {
         case LOPE_ERR_UNSUPPORTED: return "unsupported";
         case LOPE_ERR_NO_DEVICE: return "no device";
         case LOPE_ERR_HIP: return "HIP runtime error";
+        case LOPE_ERR_TIMEOUT: return "device wait timed out";
         default: return "unknown status";
     }
 }

@@ -12,27 +12,12 @@
 // out so that consecutive entries run on one XCD (workgroup b runs on XCD
 // b mod 8), keeping a grid's shared halo rows and columns in one L2.  Per
 // point the result equals lope_iterate's, value for value.
-#include "plane2d_wave.h"
+#include "batch_strip.h"
 
 namespace lope {
 namespace {
 
 constexpr int kBatchWaves = 4;   // waves per workgroup
-
-template <typename T, int TD, bool BOX>
-__device__ __forceinline__ void batch_strip(const BatchGrid& gr, const DevGrid& in, const DevGrid& out,
-                                            const T (&c9)[9], const BatchItem& it) {
-    const T g = (T)gr.rule.g;
-    const bool dx = gr.rule.per[0] == 0, dy = gr.rule.per[1] == 0;
-    if (dx && dy)
-        plane2d_wave_strip<T, TD, BOX, true, true>(in, out, g, c9, it.x0, it.y0, it.y1);
-    else if (dx)
-        plane2d_wave_strip<T, TD, BOX, true, false>(in, out, g, c9, it.x0, it.y0, it.y1);
-    else if (dy)
-        plane2d_wave_strip<T, TD, BOX, false, true>(in, out, g, c9, it.x0, it.y0, it.y1);
-    else
-        plane2d_wave_strip<T, TD, BOX, false, false>(in, out, g, c9, it.x0, it.y0, it.y1);
-}
 
 template <typename T, int TD>
 __global__ void __launch_bounds__(kBatchWaves * 64)
@@ -43,16 +28,7 @@ k_batch_wave(const BatchGrid* __restrict__ grids, const BatchItem* __restrict__ 
                   __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (w >= nitems) return;   // whole waves leave; the kernel has no barrier
     const BatchItem it = items[w];
-    const BatchGrid& gr = grids[it.grid];
-    const DevGrid in = parity ? gr.dst : gr.src;
-    const DevGrid out = parity ? gr.src : gr.dst;
-    T c9[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) c9[t] = (T)gr.c[t];
-    if (gr.box)
-        batch_strip<T, TD, true>(gr, in, out, c9, it);
-    else
-        batch_strip<T, TD, false>(gr, in, out, c9, it);
+    batch_strip<T, TD>(grids[it.grid], parity, it);
 }
 
 template <typename T, int TD>

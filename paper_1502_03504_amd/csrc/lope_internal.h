@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "lope.h"
+#include "batch_queue.h"
 
 namespace lope {
 
@@ -163,6 +164,29 @@ int batch_strip_width(int tdepth);
 // One pass of tdepth sweeps over every listed tile; parity 0 reads src, 1 reads dst.
 hipError_t launch_batch_pass(const BatchGrid* grids, const BatchItem* items, int nitems, int tdepth, int parity,
                              int dtype, hipStream_t s);
+
+// State of the persistent batched launch (one per plan, zeroed at creation;
+// the kernel's last wave leaves next, left and abort at zero again).
+struct PqState {
+    unsigned long long next;   // next unit to hand out
+    unsigned int left;         // waves that have left the loop
+    unsigned int abort;        // set when a wait ran out of time: every wave leaves
+    unsigned int timeouts;     // waits that ran out (kept; the host reads and clears it)
+    unsigned int pad[11];
+};
+// Per grid: strips completed in the running launch (reset by the last wave)
+// and the grid's strips in the full-depth table (set by the host).
+struct PqGrid {
+    unsigned int done;
+    int32_t full_strips;
+};
+// Every pass of a batch in one launch of the persistent kernel: `shape.full`
+// passes of tdepth sweeps over full_items, then (shape.n_rem > 0) one pass of
+// rem sweeps over rem_items.  wait_us bounds each dependency wait (0: a wait
+// not met at its first poll runs out).
+hipError_t launch_batch_persistent(const BatchGrid* grids, const BatchItem* full_items, const BatchItem* rem_items,
+                                   const PqShape& shape, int tdepth, int rem, PqState* st, PqGrid* pg, int ngrids,
+                                   long long wait_us, int dtype, hipStream_t s);
 
 // ---- device helpers ----
 __device__ __forceinline__ int wrap_index(int i, int n) {
