@@ -127,8 +127,9 @@ def measure_adjoint(n=256, steps=200, every=20):
 
 
 def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
-    """512 uneven 2D float32 grids, 50 sweeps each: the batched launches against
-    one launch per grid per sweep (median of reps, HIP events)."""
+    """512 uneven 2D float32 grids, 50 sweeps each: the batched launches (a
+    graph of one launch per fused pass) and the single persistent launch,
+    against one launch per grid per sweep (median of reps, HIP events)."""
     import numpy as np
     import torch
 
@@ -160,6 +161,15 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
     # batch's dtype and size (what lope_batch_apply does by default)
     depth, rows = plan.tiles()
     tb = timed(plan.apply)
+    # the same passes in one persistent kernel launch (per-grid completion
+    # counters with agent-scope release/acquire between strips), at the plan's
+    # tiling and with 256-row strips (fewer units, fewer cache flushes)
+    tpers = timed(plan.apply_persistent)
+    plan.check_persistent()
+    plan.set_tiles(depth, 256)
+    tpers256 = timed(plan.apply_persistent)
+    plan.check_persistent()
+    plan.set_tiles(depth, rows)
     tp = timed(plan.apply_per_grid, reps) if per_grid else None
     # context only: every depth at the plan's rows
     by_depth = {}
@@ -175,6 +185,7 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
             "per_grid_GPts": round(upd / (tp * 1e-3) / 1e9, 1) if tp else None,
             "speedup": round(tp / tb, 2) if tp else None,
             "batched_ms_by_depth": {str(k): round(v, 3) for k, v in by_depth.items()} or None,
+            "persistent_ms": round(tpers, 3), "persistent_ms_rows256": round(tpers256, 3),
             "launches_batched": -(-steps // depth), "launches_per_grid": steps * len(grids)}
 
 

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -770,6 +771,7 @@ struct lope_batch_plan {
     std::vector<PlanGrid> grids;
     std::vector<lope_batch_item> items;   // the items as given, coefficients pointing into grids[i].coeffs
     std::vector<int64_t> order;       // grids in tile-table order (largest first, dealt to XCD ranges)
+    std::vector<int8_t> range;        // each grid's XCD range (the order lists range 0's grids first)
     std::vector<SweepJob> jobs;       // per-grid launches (the comparison path)
     std::vector<int> job_variant;
     BatchGrid* d_grids = nullptr;
@@ -783,6 +785,7 @@ struct lope_batch_plan {
     PqState* d_pq = nullptr;
     PqGrid* d_pqg = nullptr;
     int pq_depth = 0, pq_rows = 0;
+    int pq_nq = 1;                    // queues of the persistent launch
 };
 
 namespace {
@@ -851,6 +854,7 @@ int plan_pq(lope_batch_plan* p) {
     const int rem = (int)(p->n_steps % p->tdepth);
     const int64_t bwr = rem ? batch_strip_width(rem) : 1;
     std::vector<PqGrid> hg(std::max<size_t>(n, 1));
+    std::vector<int64_t> rstrips(n);
     for (size_t i = 0; i < n; ++i) {
         const int64_t nx = p->items[i].src.n[0], ny = p->items[i].src.n[1];
         const int64_t ry = (ny + p->rows - 1) / p->rows;
@@ -861,9 +865,36 @@ int plan_pq(lope_batch_plan* p) {
             return fail(LOPE_ERR_UNSUPPORTED, "grid %zu has too many strips for one persistent launch", i);
         hg[i].done = 0;
         hg[i].full_strips = (int32_t)fs;
+        rstrips[i] = rs;
+    }
+    // one queue per XCD range: the tables list each range's grids together,
+    // so a queue's strips are one contiguous span of each table
+    const int nq = kPqMaxQueues;
+    PqQueue share[kPqMaxQueues] = {};
+    {
+        int64_t fpos = 0, rpos = 0;
+        int last = -1;
+        for (size_t k = 0; k < n; ++k) {
+            const int64_t gi = p->order[k];
+            const int q = (int)p->range[(size_t)gi];
+            if (q < last || q >= nq) return fail(LOPE_ERR_UNSUPPORTED, "batch grids not grouped by queue");
+            if (q != last) {
+                share[q].full_begin = fpos;
+                share[q].rem_begin = rpos;
+                last = q;
+            }
+            share[q].full_count += hg[(size_t)gi].full_strips;
+            share[q].rem_count += rstrips[(size_t)gi];
+            fpos += hg[(size_t)gi].full_strips;
+            rpos += rstrips[(size_t)gi];
+        }
+        if (fpos != p->nitems[p->tdepth] || (rem && rpos != p->nitems[rem]))
+            return fail(LOPE_ERR_UNSUPPORTED, "persistent batch queues do not cover the strip tables");
     }
     e = hipMemcpy(p->d_pqg, hg.data(), n * sizeof(PqGrid), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(&p->d_pq->share[0], share, sizeof(share), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "persistent batch table upload");
+    p->pq_nq = nq;
     p->pq_depth = p->tdepth;
     p->pq_rows = p->rows;
     return LOPE_OK;
@@ -1372,10 +1403,10 @@ int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_
         p->job_variant[(size_t)i] = default_variant(p->jobs[(size_t)i], 1);
     }
     p->order.resize((size_t)n_items);
+    p->range.resize((size_t)n_items);
     {
         std::vector<int64_t> sorted((size_t)n_items);
-        std::vector<int8_t> range((size_t)n_items);
-        batch_order(p->items.data(), n_items, p->order.data(), sorted.data(), range.data());
+        batch_order(p->items.data(), n_items, p->order.data(), sorted.data(), p->range.data());
     }
     std::vector<BatchGrid> hg((size_t)n_items);
     {
@@ -1488,14 +1519,15 @@ int lope_batch_apply_persistent(lope_batch_plan* plan, void* stream) {
     if (!plan->d_pq || plan->pq_depth != plan->tdepth || plan->pq_rows != plan->rows)
         return fail(LOPE_ERR_INVALID_ARG, "persistent batch state does not match the plan's tiling");
     const int rem = (int)(plan->n_steps % plan->tdepth);
-    PqShape shape;
-    shape.n_full = plan->nitems[plan->tdepth];
-    shape.n_rem = rem ? plan->nitems[rem] : 0;
+    PqShape shape{};
     shape.full = (int32_t)(plan->n_steps / plan->tdepth);
+    shape.nq = plan->pq_nq;
+    shape.take = 1;   // one unit per take: 2..8 measured slower on the 512-grid batch
+    const int64_t units = (int64_t)shape.full * plan->nitems[plan->tdepth] + (rem ? plan->nitems[rem] : 0);
     log_line("batch of %zu grids, %lld sweeps: one persistent launch, %d per pass, %d-row strips, %lld passes, "
              "%lld units",
              plan->grids.size(), (long long)plan->n_steps, plan->tdepth, plan->rows, (long long)plan_passes(plan),
-             (long long)pq_total(shape));
+             (long long)units);
     // time limit of one dependency wait: 1 s, or LOPE_PERSISTENT_WAIT_US
     // microseconds (read at each launch; 0 makes any wait not met at once run
     // out, which exercises the abort path)
@@ -1508,7 +1540,7 @@ int lope_batch_apply_persistent(lope_batch_plan* plan, void* stream) {
         wait_us = v;
     }
     const hipError_t e = launch_batch_persistent(plan->d_grids, plan->d_items[plan->tdepth],
-                                                 rem ? plan->d_items[rem] : nullptr, shape, plan->tdepth, rem,
+                                                 rem ? plan->d_items[rem] : nullptr, shape, units, plan->tdepth, rem,
                                                  plan->d_pq, plan->d_pqg, (int)plan->grids.size(), wait_us,
                                                  plan->dtype, (hipStream_t)stream);
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "persistent batch launch");

@@ -58,22 +58,35 @@ struct WaveOps {
     PqState* st;
     PqGrid* pg;
     int ngrids;
+    int nq;
     int rem;
     unsigned nwaves;
     unsigned long long wait_ticks;   // time limit of one wait
     unsigned max_polls;              // poll limit of one wait
     BatchItem it;
 
+    __device__ __forceinline__ int32_t first_queue() { return (int32_t)(blockIdx.x % (unsigned)nq); }
+    __device__ __forceinline__ PqQueue queue(int32_t q) {
+        PqQueue r;
+        r.full_begin = (int64_t)uniform((unsigned long long)st->share[q].full_begin);
+        r.full_count = (int64_t)uniform((unsigned long long)st->share[q].full_count);
+        r.rem_begin = (int64_t)uniform((unsigned long long)st->share[q].rem_begin);
+        r.rem_count = (int64_t)uniform((unsigned long long)st->share[q].rem_count);
+        return r;
+    }
     __device__ __forceinline__ bool aborted() {
         return uniform(__hip_atomic_load(&st->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0;
     }
-    __device__ __forceinline__ int64_t take() {
+    __device__ __forceinline__ int64_t take(int32_t q, int32_t n) {
         unsigned long long u = 0;
-        if (lane0()) u = __hip_atomic_fetch_add(&st->next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane0())
+            u = __hip_atomic_fetch_add(&st->queue[q].next, (unsigned long long)n, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
         return (int64_t)uniform(u);
     }
     __device__ __forceinline__ int32_t grid_of(const PqUnit& un) {
-        const BatchItem& src = un.rem ? rem_items[un.strip] : full_items[un.strip];
+        const BatchItem* tab = un.rem ? rem_items : full_items;
+        const BatchItem& src = tab[un.strip];
         it.grid = uniform(src.grid);
         it.x0 = uniform(src.x0);
         it.y0 = uniform(src.y0);
@@ -117,8 +130,9 @@ struct WaveOps {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         for (int g = (int)(threadIdx.x & 63); g < ngrids; g += 64)
             __hip_atomic_store(&pg[g].done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int q = (int)(threadIdx.x & 63); q < nq; q += 64)
+            __hip_atomic_store(&st->queue[q].next, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (lane0()) {
-            __hip_atomic_store(&st->next, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&st->abort, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&st->left, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -130,19 +144,23 @@ __global__ void __launch_bounds__(kPqWaves * 64)
 k_batch_persistent(const BatchGrid* __restrict__ grids, const BatchItem* __restrict__ full_items,
                    const BatchItem* __restrict__ rem_items, PqState* st, PqGrid* pg, PqShape shape, int rem,
                    int ngrids, unsigned nwaves, unsigned long long wait_ticks, unsigned max_polls) {
-    WaveOps<T, TD> ops{grids, full_items, rem_items, st, pg, ngrids, rem, nwaves, wait_ticks, max_polls, BatchItem{}};
+    WaveOps<T, TD> ops{grids, full_items, rem_items, st,         pg,        ngrids,
+                       shape.nq, rem,        nwaves,    wait_ticks, max_polls, BatchItem{}};
     pq_worker(ops, shape);
 }
 
 template <typename T, int TD>
 hipError_t launch_p(const BatchGrid* grids, const BatchItem* full_items, const BatchItem* rem_items,
-                    const PqShape& shape, int rem, PqState* st, PqGrid* pg, int ngrids, long long wait_us,
-                    hipStream_t s) {
+                    const PqShape& shape, int64_t units, int rem, PqState* st, PqGrid* pg, int ngrids,
+                    long long wait_us, hipStream_t s) {
     const auto kernel = k_batch_persistent<T, TD>;
     static const int bpc = blocks_per_cu(kernel, kPqWaves * 64);
-    const int64_t total = pq_total(shape);
     // as many workgroups as the device holds at once (more would only queue)
-    const int64_t nb = std::min<int64_t>((total + kPqWaves - 1) / kPqWaves, (int64_t)bpc * device_cu_count());
+    const int64_t takes = (units + shape.take - 1) / shape.take;
+    int64_t nb = std::min<int64_t>((takes + kPqWaves - 1) / kPqWaves, (int64_t)bpc * device_cu_count());
+    // workgroup b runs on XCD b mod 8: a multiple of the queue count starts
+    // waves at every queue
+    nb = (nb + shape.nq - 1) / shape.nq * shape.nq;
     // a limit of 0 makes the first poll that finds a wait unmet run out
     const unsigned long long ticks = (unsigned long long)wait_us * kPqTicksPerUs;
     const unsigned polls = wait_us > 0 ? kPqMaxPolls : 0u;
@@ -153,17 +171,17 @@ hipError_t launch_p(const BatchGrid* grids, const BatchItem* full_items, const B
 
 template <typename T>
 hipError_t launch_typed(const BatchGrid* grids, const BatchItem* full_items, const BatchItem* rem_items,
-                        const PqShape& shape, int tdepth, int rem, PqState* st, PqGrid* pg, int ngrids,
-                        long long wait_us, hipStream_t s) {
+                        const PqShape& shape, int64_t units, int tdepth, int rem, PqState* st, PqGrid* pg,
+                        int ngrids, long long wait_us, hipStream_t s) {
     switch (tdepth) {
-        case 1: return launch_p<T, 1>(grids, full_items, rem_items, shape, rem, st, pg, ngrids, wait_us, s);
-        case 2: return launch_p<T, 2>(grids, full_items, rem_items, shape, rem, st, pg, ngrids, wait_us, s);
-        case 3: return launch_p<T, 3>(grids, full_items, rem_items, shape, rem, st, pg, ngrids, wait_us, s);
-        case 4: return launch_p<T, 4>(grids, full_items, rem_items, shape, rem, st, pg, ngrids, wait_us, s);
-        case 5: return launch_p<T, 5>(grids, full_items, rem_items, shape, rem, st, pg, ngrids, wait_us, s);
-        case 6: return launch_p<T, 6>(grids, full_items, rem_items, shape, rem, st, pg, ngrids, wait_us, s);
-        case 7: return launch_p<T, 7>(grids, full_items, rem_items, shape, rem, st, pg, ngrids, wait_us, s);
-        case 8: return launch_p<T, 8>(grids, full_items, rem_items, shape, rem, st, pg, ngrids, wait_us, s);
+        case 1: return launch_p<T, 1>(grids, full_items, rem_items, shape, units, rem, st, pg, ngrids, wait_us, s);
+        case 2: return launch_p<T, 2>(grids, full_items, rem_items, shape, units, rem, st, pg, ngrids, wait_us, s);
+        case 3: return launch_p<T, 3>(grids, full_items, rem_items, shape, units, rem, st, pg, ngrids, wait_us, s);
+        case 4: return launch_p<T, 4>(grids, full_items, rem_items, shape, units, rem, st, pg, ngrids, wait_us, s);
+        case 5: return launch_p<T, 5>(grids, full_items, rem_items, shape, units, rem, st, pg, ngrids, wait_us, s);
+        case 6: return launch_p<T, 6>(grids, full_items, rem_items, shape, units, rem, st, pg, ngrids, wait_us, s);
+        case 7: return launch_p<T, 7>(grids, full_items, rem_items, shape, units, rem, st, pg, ngrids, wait_us, s);
+        case 8: return launch_p<T, 8>(grids, full_items, rem_items, shape, units, rem, st, pg, ngrids, wait_us, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -171,14 +189,15 @@ hipError_t launch_typed(const BatchGrid* grids, const BatchItem* full_items, con
 }  // namespace
 
 hipError_t launch_batch_persistent(const BatchGrid* grids, const BatchItem* full_items, const BatchItem* rem_items,
-                                   const PqShape& shape, int tdepth, int rem, PqState* st, PqGrid* pg, int ngrids,
-                                   long long wait_us, int dtype, hipStream_t s) {
-    if (pq_total(shape) <= 0) return hipSuccess;
-    if (rem < 0 || rem >= tdepth || (shape.n_rem > 0) != (rem > 0)) return hipErrorInvalidValue;
+                                   const PqShape& shape, int64_t units, int tdepth, int rem, PqState* st,
+                                   PqGrid* pg, int ngrids, long long wait_us, int dtype, hipStream_t s) {
+    if (units <= 0) return hipSuccess;
+    if (rem < 0 || rem >= tdepth || shape.nq < 1 || shape.nq > kPqMaxQueues || shape.take < 1)
+        return hipErrorInvalidValue;
     if (wait_us < 0 || wait_us > (1ll << 40)) return hipErrorInvalidValue;
     if (dtype == LOPE_F32)
-        return launch_typed<float>(grids, full_items, rem_items, shape, tdepth, rem, st, pg, ngrids, wait_us, s);
-    return launch_typed<double>(grids, full_items, rem_items, shape, tdepth, rem, st, pg, ngrids, wait_us, s);
+        return launch_typed<float>(grids, full_items, rem_items, shape, units, tdepth, rem, st, pg, ngrids, wait_us, s);
+    return launch_typed<double>(grids, full_items, rem_items, shape, units, tdepth, rem, st, pg, ngrids, wait_us, s);
 }
 
 }  // namespace lope

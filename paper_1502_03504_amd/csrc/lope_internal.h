@@ -166,13 +166,19 @@ hipError_t launch_batch_pass(const BatchGrid* grids, const BatchItem* items, int
                              int dtype, hipStream_t s);
 
 // State of the persistent batched launch (one per plan, zeroed at creation;
-// the kernel's last wave leaves next, left and abort at zero again).
+// the kernel's last wave leaves the queue counters, left and abort at zero
+// again).  Each queue counter has a 128-byte line of its own.
+struct PqCounter {
+    unsigned long long next;   // next unit of the queue to hand out
+    unsigned long long pad[15];
+};
 struct PqState {
-    unsigned long long next;   // next unit to hand out
+    PqCounter queue[kPqMaxQueues];
     unsigned int left;         // waves that have left the loop
     unsigned int abort;        // set when a wait ran out of time: every wave leaves
     unsigned int timeouts;     // waits that ran out (kept; the host reads and clears it)
-    unsigned int pad[11];
+    unsigned int pad[29];
+    PqQueue share[kPqMaxQueues];   // each queue's strips (set by the host)
 };
 // Per grid: strips completed in the running launch (reset by the last wave)
 // and the grid's strips in the full-depth table (set by the host).
@@ -181,12 +187,12 @@ struct PqGrid {
     int32_t full_strips;
 };
 // Every pass of a batch in one launch of the persistent kernel: `shape.full`
-// passes of tdepth sweeps over full_items, then (shape.n_rem > 0) one pass of
-// rem sweeps over rem_items.  wait_us bounds each dependency wait (0: a wait
+// passes of tdepth sweeps over full_items, then (rem > 0) one pass of rem
+// sweeps over rem_items; `units` is the total over the queues.  wait_us bounds each dependency wait (0: a wait
 // not met at its first poll runs out).
 hipError_t launch_batch_persistent(const BatchGrid* grids, const BatchItem* full_items, const BatchItem* rem_items,
-                                   const PqShape& shape, int tdepth, int rem, PqState* st, PqGrid* pg, int ngrids,
-                                   long long wait_us, int dtype, hipStream_t s);
+                                   const PqShape& shape, int64_t units, int tdepth, int rem, PqState* st,
+                                   PqGrid* pg, int ngrids, long long wait_us, int dtype, hipStream_t s);
 
 // ---- device helpers ----
 __device__ __forceinline__ int wrap_index(int i, int n) {
