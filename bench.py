@@ -162,12 +162,12 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
     depth, rows = plan.tiles()
     tb = timed(plan.apply)
     # the same passes in one persistent kernel launch (per-grid completion
-    # counters with agent-scope release/acquire between strips), at the plan's
-    # tiling and with 256-row strips (fewer units, fewer cache flushes)
+    # counters, device-scope grid accesses), at the plan's tiling and at the
+    # tiling measured fastest for it (8 sweeps per pass, 256-row strips)
     tpers = timed(plan.apply_persistent)
     plan.check_persistent()
-    plan.set_tiles(depth, 256)
-    tpers256 = timed(plan.apply_persistent)
+    plan.set_tiles(8, 256)
+    tpers8 = timed(plan.apply_persistent)
     plan.check_persistent()
     plan.set_tiles(depth, rows)
     tp = timed(plan.apply_per_grid, reps) if per_grid else None
@@ -185,7 +185,8 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
             "per_grid_GPts": round(upd / (tp * 1e-3) / 1e9, 1) if tp else None,
             "speedup": round(tp / tb, 2) if tp else None,
             "batched_ms_by_depth": {str(k): round(v, 3) for k, v in by_depth.items()} or None,
-            "persistent_ms": round(tpers, 3), "persistent_ms_rows256": round(tpers256, 3),
+            "persistent_ms": round(tpers, 3), "persistent_ms_t8_rows256": round(tpers8, 3),
+            "persistent_GPts_t8_rows256": round(upd / (tpers8 * 1e-3) / 1e9, 1),
             "launches_batched": -(-steps // depth), "launches_per_grid": steps * len(grids)}
 
 

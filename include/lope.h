@@ -354,15 +354,17 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream);
  * batched sweep; the sweep and the double buffering of sections 3.2-3.3 for
  * every grid): the kernel's waves take work units, one strip of one grid in
  * one pass each, from a queue numbered pass by pass, and a unit starts once
- * every strip of its grid's earlier passes is complete (per-grid counters,
- * agent-scope release and acquire).  A wave waits only on units handed out
+ * every strip of its grid's earlier passes is complete (per-grid counters;
+ * the kernel's grid loads and stores are device-scope, so no cache flush is
+ * needed between strips).  A wave waits only on units handed out
  * before its own, so the queue cannot deadlock whatever the number of
  * resident waves; every wait is also bounded (1 s, or the environment's
  * LOPE_PERSISTENT_WAIT_US microseconds, read at each call; 0 makes any wait
  * not met at once run out), and one that runs out makes all waves leave early
  * (see lope_batch_persistent_check).  The result
  * equals lope_batch_apply's value for value, in the buffer
- * lope_batch_result_index names, with the plan's tiling.  Enqueued on
+ * lope_batch_result_index names, with the plan's tiling (8 sweeps per pass
+ * and 256-row strips were fastest on the 512-grid batch).  Enqueued on
  * `stream` with no other operation, so a caller may capture it into a graph
  * as one kernel node; the kernel's last wave clears the plan's queue for the
  * next launch.  Launches of one plan must not overlap (they share its queue):

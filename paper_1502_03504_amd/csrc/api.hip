@@ -1522,7 +1522,7 @@ int lope_batch_apply_persistent(lope_batch_plan* plan, void* stream) {
     PqShape shape{};
     shape.full = (int32_t)(plan->n_steps / plan->tdepth);
     shape.nq = plan->pq_nq;
-    shape.take = 1;   // one unit per take: 2..8 measured slower on the 512-grid batch
+    shape.take = 1;   // one unit per take
     const int64_t units = (int64_t)shape.full * plan->nitems[plan->tdepth] + (rem ? plan->nitems[rem] : 0);
     log_line("batch of %zu grids, %lld sweeps: one persistent launch, %d per pass, %d-row strips, %lld passes, "
              "%lld units",

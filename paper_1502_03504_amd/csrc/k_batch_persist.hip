@@ -9,12 +9,17 @@
 // so waves of one launch work on several passes at once wherever the grids'
 // dependencies allow, with no kernel boundary between passes.
 //
-// Memory ordering (agent scope, since a grid's strips run on any XCD): the
-// wave publishes its strip with a release fence (its stores complete and the
-// XCD's L2 written back) before adding to the grid's counter; a waiting wave
-// polls the counter with relaxed atomic loads and, once it is high enough,
-// takes an acquire fence (L1 and L2 invalidated) before reading the strip's
-// inputs.  Every wait is bounded (wall clock and poll count); one that runs
+// Memory ordering: a grid's strips run on any XCD, and the XCDs' L2 caches
+// are not coherent with each other, so every load and store of grid data in
+// this kernel is a device-scope (agent) access (batch_strip with DEV): loads
+// read past every cache that could hold an older copy, and a store is
+// complete only once every XCD can see it.  A wave then publishes its strip
+// by waiting for its stores to complete before adding to the grid's counter
+// (an agent-scope atomic), and a waiting wave polls the counter with relaxed
+// agent-scope loads; no cache write-back or invalidation is needed per strip.
+// (The same ordering by agent-scope release and acquire fences around plain
+// accesses, which flush and invalidate the L2 at every strip, is 3-6x slower
+// here.)  Every wait is bounded (wall clock and poll count); one that runs
 // out sets the abort flag and counts a timeout, and every wave leaves.
 #include "batch_strip.h"
 
@@ -45,7 +50,7 @@ __device__ __forceinline__ void strip_at_depth(const BatchGrid& gr, int parity, 
             return;
         }
     }
-    batch_strip<T, TD>(gr, parity, it);
+    batch_strip<T, TD, true>(gr, parity, it);
 }
 
 // The worker policy of one wave (every member function is called by all 64
@@ -109,14 +114,18 @@ struct WaveOps {
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // the strip's loads are device-scope: they read past every cache that
+        // could hold an older copy; only the compiler must keep them after the poll
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         return true;
     }
     __device__ __forceinline__ void run(const PqUnit& un) {
         strip_at_depth<T, TD>(grids[it.grid], un.pass & 1, it, un.rem ? rem : TD);
     }
     __device__ __forceinline__ void complete(int32_t g) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // the strip's stores are device-scope: once complete they are visible
+        // to every XCD, so waiting for them is the whole release
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         // every lane adds (lane 0 adds the one), so each lane's stores are
         // ordered before the count by its own fence
         __hip_atomic_fetch_add(&pg[g].done, lane0() ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -28,6 +28,10 @@
 // STG (TD = 2) it makes one two-stage step: level 1 applies c9, level 2 the
 // second table c9b plus alpha times the starting state (STG = 2).
 //
+// With DEV every load and store of the grid is a device-scope (agent) access,
+// coherent across XCDs without cache flushes (the persistent batched launch,
+// where strips of one grid run on any XCD within one kernel).
+//
 // Every argument must be uniform across the wave, and all 64 lanes must be
 // active (the DPP shifts read every lane).
 #pragma once
@@ -86,7 +90,7 @@ __device__ __forceinline__ void wave_steps(int j, int jend, F& f) {
     }
 }
 
-template <typename T, int TD, bool BOX, bool DX, bool DY, bool RES = false, int STG = 0>
+template <typename T, int TD, bool BOX, bool DX, bool DY, bool RES = false, int STG = 0, bool DEV = false>
 __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const DevGrid& dst, T g, const T (&c9)[9],
                                                    int x0, int y0, int yend, double* residual = nullptr,
                                                    const T* c9b = nullptr, T alpha = (T)0) {
@@ -112,7 +116,12 @@ __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const Dev
     const char* lp = sbase + (int64_t)lw * sbytes;
     auto next_row = [&]() -> T {
         T v = g;   // raw value: the x rule is applied when the row enters level 0
-        if (!DY || (lj >= 0 && lj < ny)) v = *(const T*)(lp + coff);
+        if (!DY || (lj >= 0 && lj < ny)) {
+            if constexpr (DEV)
+                v = __hip_atomic_load((T*)(lp + coff), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                v = *(const T*)(lp + coff);
+        }
         ++lj;
         ++lw;
         lp += sbytes;
@@ -189,7 +198,10 @@ __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const Dev
             if (DY && (yk < 0 || yk >= ny)) v = g;
             if (k == TD) {
                 if (keep && yk >= y0 && yk < yend) {
-                    __builtin_nontemporal_store(v, (T*)sp_out);
+                    if constexpr (DEV)
+                        __hip_atomic_store((T*)sp_out, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    else
+                        __builtin_nontemporal_store(v, (T*)sp_out);
                     // the centre of level TD-1 is the state before the last sweep
                     if (RES) rmax = nan_max(rmax, fabs((double)v - (double)r[S1][1]));
                 }
