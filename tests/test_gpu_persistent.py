@@ -215,3 +215,39 @@ def test_persistent_batch_512_grids_matches_passes():
     for i in range(len(grids)):
         assert torch.equal(plan.result(i).interior(), ref[i]), i
     plan.close()
+
+
+def test_persistent_batch_repeated_launches_stay_exact():
+    """Coherence under load: the 512-grid batch at three tilings, six
+    persistent launches each (from a reset state, and two in a row), every
+    grid equal to the per-pass launches value for value every time."""
+    print("persistent batch: repeated launches of the 512-grid batch", flush=True)
+    grids, steps = synth.case_batch()
+    entries = [(grid_from(g.field, 1), empty_grid(g.field.shape, 1, np.float32), g.stencil, g.bc) for g in grids]
+    fields = [g.field for g in grids]
+    plan = L.BatchPlan(entries, steps)
+    for depth, rows in [(8, 256), (3, 128), (5, 32)]:
+        plan.set_tiles(depth, rows)
+        _reset(entries, fields)
+        plan.apply()
+        torch.cuda.synchronize()
+        ref = _results(plan, len(grids))
+        _reset(entries, fields)
+        plan.apply()
+        plan.apply()
+        torch.cuda.synchronize()
+        ref2 = _results(plan, len(grids))
+        for rep in range(4):
+            _reset(entries, fields)
+            plan.apply_persistent()
+            plan.check_persistent()
+            bad = [i for i in range(len(grids)) if not torch.equal(plan.result(i).interior(), ref[i])]
+            assert not bad, (depth, rows, rep, bad[:5])
+        for rep in range(2):
+            _reset(entries, fields)
+            plan.apply_persistent()
+            plan.apply_persistent()
+            plan.check_persistent()
+            bad = [i for i in range(len(grids)) if not torch.equal(plan.result(i).interior(), ref2[i])]
+            assert not bad, (depth, rows, "two in a row", rep, bad[:5])
+    plan.close()
