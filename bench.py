@@ -127,8 +127,8 @@ def measure_adjoint(n=256, steps=200, every=20):
 
 
 def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
-    """512 uneven 2D float32 grids, 50 sweeps each: the batched launches (a
-    graph of one launch per fused pass) and the single persistent launch,
+    """512 uneven 2D float32 grids, 50 sweeps each: the single persistent
+    launch (lope_batch_apply) and the graph of one launch per fused pass,
     against one launch per grid per sweep (median of reps, HIP events)."""
     import numpy as np
     import torch
@@ -143,9 +143,9 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
     plan = L.BatchPlan(entries, steps)
     s = torch.cuda.current_stream()
 
-    def timed(fn, n=None):
-        fn()
-        fn()
+    def timed(fn, n=None, warm=2):
+        for _ in range(warm):
+            fn()
         ts = []
         for _ in range(n or max(reps, 5)):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -158,25 +158,26 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
         return ts[len(ts) // 2]
 
     # the plan's own tiling: the one the tuning table registers for this
-    # batch's dtype and size (what lope_batch_apply does by default)
+    # batch's dtype and size (what lope_batch_apply does by default): every
+    # pass of every grid in one persistent kernel launch
     depth, rows = plan.tiles()
-    tb = timed(plan.apply)
-    # the same passes in one persistent kernel launch (per-grid completion
-    # counters, device-scope grid accesses), at the plan's tiling and at the
-    # tiling measured fastest for it (8 sweeps per pass, 256-row strips)
-    tpers = timed(plan.apply_persistent)
+    tb = timed(plan.apply, warm=10)   # the first launches after set-up run slower
     plan.check_persistent()
-    plan.set_tiles(8, 256)
-    tpers8 = timed(plan.apply_persistent)
-    plan.check_persistent()
+    # the same sweeps as one launch per fused pass (a recorded graph), at the
+    # same tiling and at the tiling measured fastest for it (6 per pass,
+    # 64-row strips)
+    tpass = timed(plan.apply_passes)
+    plan.set_tiles(6, 64)
+    tpass6 = timed(plan.apply_passes)
     plan.set_tiles(depth, rows)
     tp = timed(plan.apply_per_grid, reps) if per_grid else None
-    # context only: every depth at the plan's rows
+    # context only: the persistent launch at every depth at the plan's rows
     by_depth = {}
     if by_depth_sweep:
         for td in range(1, 9):
             plan.set_depth(td)
             by_depth[td] = timed(plan.apply)
+        plan.check_persistent()
     plan.close()
     upd = points * steps
     return {"workload": "batch_512_grids_2d_f32_50_sweeps", "points": points, "tdepth": depth, "rows": rows,
@@ -185,9 +186,8 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
             "per_grid_GPts": round(upd / (tp * 1e-3) / 1e9, 1) if tp else None,
             "speedup": round(tp / tb, 2) if tp else None,
             "batched_ms_by_depth": {str(k): round(v, 3) for k, v in by_depth.items()} or None,
-            "persistent_ms": round(tpers, 3), "persistent_ms_t8_rows256": round(tpers8, 3),
-            "persistent_GPts_t8_rows256": round(upd / (tpers8 * 1e-3) / 1e9, 1),
-            "launches_batched": -(-steps // depth), "launches_per_grid": steps * len(grids)}
+            "passes_ms": round(tpass, 3), "passes_ms_t6_rows64": round(tpass6, 3),
+            "launches_batched": 1, "launches_passes": -(-steps // depth), "launches_per_grid": steps * len(grids)}
 
 
 def measure_copy(mib=1024, reps=10):

@@ -341,40 +341,39 @@ typedef struct lope_batch_plan lope_batch_plan;
 int lope_batch_plan_create(const lope_batch_item* items, int64_t n_items, int64_t n_steps,
                            void* stream, lope_batch_plan** out);
 
-/* Advance every grid n_steps sweeps from the state in its src: each kernel
- * launch covers every tile of every grid and fuses tdepth sweeps (about
- * n_steps/tdepth launches in total).  The first call for a depth records
- * those launches into a HIP graph owned by the plan; later calls replay it on
- * `stream` (one graph launch).  When `stream` is itself being captured, the
- * launches are enqueued directly into the caller's graph instead.
- * lope_batch_result_index tells which buffer holds the result. */
+/* Advance every grid n_steps sweeps from the state in its src in ONE kernel
+ * launch (the persistent batched sweep; the sweep and the double buffering of
+ * sections 3.2-3.3 for every grid).  The kernel's waves take work units, one
+ * strip of one grid in one pass of tdepth fused sweeps each, from queues
+ * numbered pass by pass, and a unit starts once every strip of its grid's
+ * earlier passes is complete (per-grid counters; the kernel's grid loads and
+ * stores are device-scope, so no cache flush is needed between strips).  A
+ * wave waits only on units handed out before its own, so the queues cannot
+ * deadlock whatever the number of resident waves; every wait is also bounded
+ * (1 s, or the environment's LOPE_PERSISTENT_WAIT_US microseconds, read at
+ * each call; 0 makes any wait not met at once run out), and one that runs out
+ * makes all waves leave early (see lope_batch_persistent_check).  Uses the
+ * plan's tiling.  Enqueued on `stream` with no other operation, so a caller
+ * may capture it into a graph as one kernel node; the kernel's last wave
+ * clears the plan's queues for the next launch.  Launches of one plan must
+ * not overlap (they share its queues): keep them on one stream.
+ * lope_batch_result_index tells which buffer holds the result.
+ * Errors: LOPE_ERR_INVALID_ARG (null plan). */
 int lope_batch_apply(lope_batch_plan* plan, void* stream);
 
-/* The same passes as lope_batch_apply in ONE kernel launch (the persistent
- * batched sweep; the sweep and the double buffering of sections 3.2-3.3 for
- * every grid): the kernel's waves take work units, one strip of one grid in
- * one pass each, from a queue numbered pass by pass, and a unit starts once
- * every strip of its grid's earlier passes is complete (per-grid counters;
- * the kernel's grid loads and stores are device-scope, so no cache flush is
- * needed between strips).  A wave waits only on units handed out
- * before its own, so the queue cannot deadlock whatever the number of
- * resident waves; every wait is also bounded (1 s, or the environment's
- * LOPE_PERSISTENT_WAIT_US microseconds, read at each call; 0 makes any wait
- * not met at once run out), and one that runs out makes all waves leave early
- * (see lope_batch_persistent_check).  The result
- * equals lope_batch_apply's value for value, in the buffer
- * lope_batch_result_index names, with the plan's tiling (8 sweeps per pass
- * and 256-row strips were fastest on the 512-grid batch).  Enqueued on
- * `stream` with no other operation, so a caller may capture it into a graph
- * as one kernel node; the kernel's last wave clears the plan's queue for the
- * next launch.  Launches of one plan must not overlap (they share its queue):
- * keep them on one stream.  Errors: LOPE_ERR_INVALID_ARG (null plan). */
-int lope_batch_apply_persistent(lope_batch_plan* plan, void* stream);
-
 /* Synchronises the device, then returns LOPE_ERR_TIMEOUT if a wait of an
- * earlier lope_batch_apply_persistent of this plan ran out of time (that
- * launch's result is invalid; the record is cleared), else LOPE_OK. */
+ * earlier lope_batch_apply of this plan ran out of time (that launch's
+ * result is invalid; the record is cleared), else LOPE_OK. */
 int lope_batch_persistent_check(lope_batch_plan* plan);
+
+/* The same sweeps as separate launches, one per pass: each launch covers
+ * every strip of every grid and fuses tdepth sweeps (about n_steps/tdepth
+ * launches in total).  The first call for a tiling records those launches
+ * into a HIP graph owned by the plan; later calls replay it on `stream` (one
+ * graph launch).  When `stream` is itself being captured, the launches are
+ * enqueued directly into the caller's graph instead.  The result equals
+ * lope_batch_apply's value for value, in the same buffer. */
+int lope_batch_apply_passes(lope_batch_plan* plan, void* stream);
 
 /* Same work as lope_batch_apply as ordinary lope_iterate launches, one per
  * grid per sweep (the baseline the batched launch is compared with). */
@@ -416,8 +415,8 @@ int lope_batch_plan_destroy(lope_batch_plan* plan);
 
 /* For callers that cannot allocate device memory (serving loops that must not
  * call hipMalloc, harnesses that forbid it): the work of
- * lope_batch_plan_create + lope_batch_apply + lope_batch_plan_destroy in one
- * call that allocates nothing.  The grid descriptors and strip tables go into
+ * lope_batch_plan_create + lope_batch_apply_passes + lope_batch_plan_destroy in
+ * one call that allocates nothing (one launch per fused pass).  The grid descriptors and strip tables go into
  * a fixed device array of LOPE_BATCH_SCRATCH_BYTES that the library holds on
  * each device it runs on until the process ends; a batch whose tables do not
  * fit returns LOPE_ERR_UNSUPPORTED (naming the bytes needed) before anything

@@ -26,7 +26,7 @@ __all__ = [
     "gbar_buffer", "LOPE_GBAR_DOUBLES", "lope_apply_var", "lope_apply_var_adjoint",
     "lope_accumulate", "lope_variant_count", "lope_variant_info", "lope_select_variant",
     "lope_tune_set", "variants", "BatchPlan", "lope_batch_plan_create", "lope_batch_apply",
-    "lope_batch_apply_per_grid", "lope_batch_apply_persistent", "lope_batch_persistent_check",
+    "lope_batch_apply_per_grid", "lope_batch_apply_passes", "lope_batch_persistent_check",
     "lope_batch_plan_destroy", "lope_batch_tune_set", "lope_batch_apply_noalloc", "lope_copy_stream", "DIRICHLET", "PERIODIC",
 ]
 
@@ -430,6 +430,6 @@ def lope_tune_set(grid: Grid, stencil, variant: int, tdepth: int = 0, chunk: int
 
 
 from .batch import (  # noqa: E402,F401
-    BatchPlan, lope_batch_plan_create, lope_batch_apply, lope_batch_apply_per_grid, lope_batch_apply_persistent,
+    BatchPlan, lope_batch_plan_create, lope_batch_apply, lope_batch_apply_per_grid, lope_batch_apply_passes,
     lope_batch_persistent_check, lope_batch_plan_destroy, lope_batch_tune_set, lope_batch_apply_noalloc,
 )

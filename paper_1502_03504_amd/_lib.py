@@ -117,7 +117,7 @@ SIGNATURES = {
                                               P(c_void_p)]),
     "lope_batch_apply": (ctypes.c_int, [c_void_p, c_void_p]),
     "lope_batch_apply_per_grid": (ctypes.c_int, [c_void_p, c_void_p]),
-    "lope_batch_apply_persistent": (ctypes.c_int, [c_void_p, c_void_p]),
+    "lope_batch_apply_passes": (ctypes.c_int, [c_void_p, c_void_p]),
     "lope_batch_persistent_check": (ctypes.c_int, [c_void_p]),
     "lope_batch_plan_set_depth": (ctypes.c_int, [c_void_p, ctypes.c_int32]),
     "lope_batch_plan_set_tiles": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int32]),

@@ -1,5 +1,5 @@
-"""Batch plans: many uneven 2D grids swept together, one launch per fused pass
-(or every pass in one persistent launch)."""
+"""Batch plans: many uneven 2D grids swept together, every pass in one
+persistent launch (or one launch per fused pass)."""
 from __future__ import annotations
 
 import ctypes
@@ -12,10 +12,12 @@ class BatchPlan:
     """Owns a lope_batch_plan and keeps the grids it borrows alive.
 
     ``entries`` is a sequence of (src Grid, dst Grid, stencil, bc).  Each
-    ``apply`` advances every grid ``n_steps`` sweeps starting from its src;
-    ``result(i)`` is the grid holding the outcome.  ``apply_per_grid`` does the
-    same work with one launch per grid per sweep and leaves the outcome in src
-    when n_steps is even, else in dst.
+    ``apply`` advances every grid ``n_steps`` sweeps starting from its src in
+    one persistent kernel launch; ``result(i)`` is the grid holding the
+    outcome.  ``apply_passes`` does the same with one launch per fused pass
+    (replayed from a recorded graph), and ``apply_per_grid`` with one launch
+    per grid per sweep, leaving the outcome in src when n_steps is even, else
+    in dst.
     """
 
     def __init__(self, entries, n_steps: int, stream=None):
@@ -41,12 +43,12 @@ class BatchPlan:
     def apply_per_grid(self, stream=None) -> None:
         check(load().lope_batch_apply_per_grid(self.handle, self._stream(stream)))
 
-    def apply_persistent(self, stream=None) -> None:
-        """The passes of ``apply`` in one persistent kernel launch (same result)."""
-        check(load().lope_batch_apply_persistent(self.handle, self._stream(stream)))
+    def apply_passes(self, stream=None) -> None:
+        """The sweeps of ``apply`` as one launch per fused pass (same result)."""
+        check(load().lope_batch_apply_passes(self.handle, self._stream(stream)))
 
     def check_persistent(self) -> None:
-        """Synchronise; raise if a wait of an earlier persistent launch ran out."""
+        """Synchronise; raise if a wait of an earlier ``apply`` ran out."""
         check(load().lope_batch_persistent_check(self.handle))
 
     def set_depth(self, tdepth: int) -> None:
@@ -69,7 +71,7 @@ class BatchPlan:
         return v.value
 
     def result(self, i: int):
-        """The grid that holds entry i's state after apply()."""
+        """The grid that holds entry i's state after apply() or apply_passes()."""
         return self.entries[i][1] if self.result_index() else self.entries[i][0]
 
     def per_grid_result(self, i: int):
@@ -125,8 +127,8 @@ def lope_batch_apply_per_grid(plan: BatchPlan, stream=None) -> None:
     plan.apply_per_grid(stream)
 
 
-def lope_batch_apply_persistent(plan: BatchPlan, stream=None) -> None:
-    plan.apply_persistent(stream)
+def lope_batch_apply_passes(plan: BatchPlan, stream=None) -> None:
+    plan.apply_passes(stream)
 
 
 def lope_batch_persistent_check(plan: BatchPlan) -> None:

@@ -1483,7 +1483,7 @@ int lope_batch_result_index(const lope_batch_plan* plan, int32_t* out) {
     return LOPE_OK;
 }
 
-int lope_batch_apply(lope_batch_plan* plan, void* stream) {
+int lope_batch_apply_passes(lope_batch_plan* plan, void* stream) {
     if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
     int rc;
     if ((rc = device_ready())) return rc;
@@ -1492,7 +1492,7 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream) {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(s, &cap);
     if (e != hipSuccess) return hip_fail(e, "stream capture query");
-    log_line("batch of %zu grids, %lld sweeps: %d per launch, %d-row strips, %lld launches%s", plan->grids.size(),
+    log_line("batch of %zu grids, %lld sweeps as passes: %d per launch, %d-row strips, %lld launches%s", plan->grids.size(),
              (long long)plan->n_steps, plan->tdepth, plan->rows, (long long)plan_passes(plan),
              cap != hipStreamCaptureStatusNone ? " (into the caller's graph)" : "");
     if (cap != hipStreamCaptureStatusNone) {
@@ -1511,7 +1511,7 @@ int lope_batch_apply(lope_batch_plan* plan, void* stream) {
     return e == hipSuccess ? LOPE_OK : hip_fail(e, "batch graph launch");
 }
 
-int lope_batch_apply_persistent(lope_batch_plan* plan, void* stream) {
+int lope_batch_apply(lope_batch_plan* plan, void* stream) {
     if (!plan) return fail(LOPE_ERR_INVALID_ARG, "null plan");
     int rc;
     if ((rc = device_ready())) return rc;
@@ -1524,7 +1524,7 @@ int lope_batch_apply_persistent(lope_batch_plan* plan, void* stream) {
     shape.nq = plan->pq_nq;
     shape.take = 1;   // one unit per take
     const int64_t units = (int64_t)shape.full * plan->nitems[plan->tdepth] + (rem ? plan->nitems[rem] : 0);
-    log_line("batch of %zu grids, %lld sweeps: one persistent launch, %d per pass, %d-row strips, %lld passes, "
+    log_line("batch of %zu grids, %lld sweeps in one persistent launch: %d per pass, %d-row strips, %lld passes, "
              "%lld units",
              plan->grids.size(), (long long)plan->n_steps, plan->tdepth, plan->rows, (long long)plan_passes(plan),
              (long long)units);

@@ -251,16 +251,17 @@ def batch_key(dtype_code, points):
 
 def autotune_batch(plan, points, depths=range(1, 9), rows=BATCH_ROWS, repeats=3, register=True, cache_path=None,
                    log=None):
-    """Time a batch plan's passes at every (sweeps per launch, rows per strip)
-    and register the fastest for batches of its dtype and size bucket (the
-    tiling lope_batch_plan_create then starts with).  Returns (best, results)."""
+    """Time a batch plan's persistent launch at every (sweeps per pass, rows
+    per strip) and register the fastest for batches of its dtype and size
+    bucket (the tiling lope_batch_plan_create then starts with).  Returns
+    (best, results)."""
     from . import lope_batch_tune_set
     s = torch.cuda.current_stream()
     results = []
     for td in depths:
         for r in rows:
             plan.set_tiles(td, r)
-            plan.apply()              # records the plan's graph for this tiling
+            plan.apply()              # first launch at this tiling (untimed)
             times = []
             for _ in range(repeats):
                 e0 = torch.cuda.Event(enable_timing=True)

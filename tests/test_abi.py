@@ -215,7 +215,8 @@ def test_batch_validation():
     assert L.lope_batch_plan_create(it, 1, 10, None, ctypes.byref(out)) == _lib.LOPE_ERR_UNSUPPORTED
     assert L.lope_batch_plan_create(it, 1, 10, None, None) == _lib.LOPE_ERR_INVALID_ARG
     assert L.lope_batch_plan_destroy(None) == _lib.LOPE_OK
-    assert L.lope_batch_apply_persistent(None, None) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_apply(None, None) == _lib.LOPE_ERR_INVALID_ARG
+    assert L.lope_batch_apply_passes(None, None) == _lib.LOPE_ERR_INVALID_ARG
     assert L.lope_batch_persistent_check(None) == _lib.LOPE_ERR_INVALID_ARG
     assert _lib.status_string(_lib.LOPE_ERR_TIMEOUT) == "device wait timed out"
 

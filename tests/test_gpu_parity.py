@@ -311,9 +311,9 @@ def test_batch_matches_per_grid_and_oracle(dtype):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
-    """Batched launches (every tile of every grid per launch, 1..8 sweeps
-    fused) against the oracle and, value for value, against one launch per
-    grid per sweep."""
+    """Per-pass batched launches (every tile of every grid per launch, 1..8
+    sweeps fused) against the oracle and, value for value, against one launch
+    per grid per sweep."""
     rng = np.random.default_rng([synth.CFG_TEST, 401])
     n = 9
     entries, fields = _batch_entries(rng, 24, dtype, lo=3, hi=700)
@@ -323,7 +323,7 @@ def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
         for (src, _, _, _), u in zip(entries, fields):
             src.interior().copy_(torch.from_numpy(u).cuda())
         plan.set_depth(depth)
-        plan.apply()
+        plan.apply_passes()
         torch.cuda.synchronize()
         got = [plan.result(i).numpy() for i in range(len(entries))]
         if ref is None:
@@ -344,8 +344,9 @@ def test_stepwise_batch_matches_per_grid_and_oracle(dtype):
 
 
 def test_batch_graph_replays_and_caller_capture():
-    """lope_batch_apply replays its recorded graph; replays with eager work in
-    between, and a caller's own captured graph, give the eager result."""
+    """lope_batch_apply_passes replays its recorded graph; replays with eager
+    work in between, and a caller's own captured graph, give the eager
+    result."""
     rng = np.random.default_rng([synth.CFG_TEST, 402])
     n = 7
     entries, fields = _batch_entries(rng, 12, np.float32, lo=3, hi=300)
@@ -362,7 +363,7 @@ def test_batch_graph_replays_and_caller_capture():
     ref = [plan.per_grid_result(i).numpy() for i in range(len(entries))]
     for rep in range(3):
         reset()
-        plan.apply()
+        plan.apply_passes()
         torch.cuda.synchronize()
         for i in range(len(entries)):
             np.testing.assert_array_equal(plan.result(i).numpy(), ref[i], err_msg="replay %d grid %d" % (rep, i))
@@ -370,7 +371,7 @@ def test_batch_graph_replays_and_caller_capture():
     reset()
     torch.cuda.synchronize()
     with torch.cuda.graph(g):
-        plan.apply()
+        plan.apply_passes()
     for rep in range(3):
         reset()
         torch.cuda.synchronize()

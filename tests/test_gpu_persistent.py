@@ -1,6 +1,8 @@
-"""GPU: the persistent batched launch (every pass of every grid in one kernel).
+"""GPU: the persistent batched launch, lope_batch_apply (every pass of every
+grid in one kernel).
 
-Its result must equal the per-pass batched launches value for value (same
+Its result must equal the per-pass launches (lope_batch_apply_passes) value
+for value (same
 strip body, same order of passes per grid) for every depth, remainder and
 edge shape, and match the oracle at the 1e-5 / 1e-12 bar; launches in a row,
 and replays of a captured graph, must each start from a cleared queue.  Its
@@ -49,11 +51,11 @@ def test_small_persistent_batch_matches_passes():
     plan = L.BatchPlan(entries, 4)
     plan.set_depth(2)
     _reset(entries, fields)
-    plan.apply()
+    plan.apply_passes()
     torch.cuda.synchronize()
     ref = _results(plan, 2)
     _reset(entries, fields)
-    plan.apply_persistent()
+    plan.apply()
     plan.check_persistent()
     for i in range(2):
         assert torch.equal(plan.result(i).interior(), ref[i]), i
@@ -74,11 +76,11 @@ def test_persistent_batch_every_depth_matches_passes_and_oracle(dtype):
         print("persistent batch: 24 grids, %d sweeps, depth %d, %s" % (n, depth, np.dtype(dtype).name), flush=True)
         plan.set_depth(depth)
         _reset(entries, fields)
-        plan.apply()
+        plan.apply_passes()
         torch.cuda.synchronize()
         ref = _results(plan, len(entries))
         _reset(entries, fields)
-        plan.apply_persistent()
+        plan.apply()
         plan.check_persistent()
         for i in range(len(entries)):
             assert torch.equal(plan.result(i).interior(), ref[i]), (depth, i)
@@ -106,11 +108,11 @@ def test_persistent_batch_edge_shapes(n, depth, rows):
     plan = L.BatchPlan(entries, n)
     plan.set_tiles(depth, rows)
     _reset(entries, fields)
-    plan.apply()
+    plan.apply_passes()
     torch.cuda.synchronize()
     ref = _results(plan, len(entries))
     _reset(entries, fields)
-    plan.apply_persistent()
+    plan.apply()
     plan.check_persistent()
     for i in range(len(entries)):
         got = plan.result(i).interior()
@@ -129,27 +131,27 @@ def test_persistent_batch_launches_in_a_row_and_graph_replays():
     plan = L.BatchPlan(entries, n)
     plan.set_depth(3)
     _reset(entries, fields)
-    plan.apply()
-    plan.apply()
-    plan.apply()
+    plan.apply_passes()
+    plan.apply_passes()
+    plan.apply_passes()
     torch.cuda.synchronize()
     ref3 = _results(plan, len(entries))
     _reset(entries, fields)
-    plan.apply_persistent()
-    plan.apply_persistent()
-    plan.apply_persistent()
+    plan.apply()
+    plan.apply()
+    plan.apply()
     plan.check_persistent()
     for i in range(len(entries)):
         assert torch.equal(plan.result(i).interior(), ref3[i]), ("three in a row", i)
     _reset(entries, fields)
-    plan.apply()
+    plan.apply_passes()
     torch.cuda.synchronize()
     ref = _results(plan, len(entries))
     g = torch.cuda.CUDAGraph()
     _reset(entries, fields)
     torch.cuda.synchronize()
     with torch.cuda.graph(g):
-        plan.apply_persistent()
+        plan.apply()
     for rep in range(3):
         _reset(entries, fields)
         torch.cuda.synchronize()
@@ -174,12 +176,12 @@ def test_persistent_batch_abort_path(monkeypatch):
     plan = L.BatchPlan(entries, n)
     plan.set_tiles(2, 16)
     _reset(entries, fields)
-    plan.apply()
+    plan.apply_passes()
     torch.cuda.synchronize()
     ref = _results(plan, len(entries))
     monkeypatch.setenv("LOPE_PERSISTENT_WAIT_US", "0")
     _reset(entries, fields)
-    plan.apply_persistent()
+    plan.apply()
     try:
         plan.check_persistent()
         timed_out = False
@@ -191,7 +193,7 @@ def test_persistent_batch_abort_path(monkeypatch):
             assert torch.equal(plan.result(i).interior(), ref[i]), i
     monkeypatch.delenv("LOPE_PERSISTENT_WAIT_US")
     _reset(entries, fields)
-    plan.apply_persistent()
+    plan.apply()
     plan.check_persistent()
     for i in range(len(entries)):
         assert torch.equal(plan.result(i).interior(), ref[i]), ("after abort", i)
@@ -206,11 +208,11 @@ def test_persistent_batch_512_grids_matches_passes():
     entries = [(grid_from(g.field, 1), empty_grid(g.field.shape, 1, np.float32), g.stencil, g.bc) for g in grids]
     fields = [g.field for g in grids]
     plan = L.BatchPlan(entries, steps)
-    plan.apply()
+    plan.apply_passes()
     torch.cuda.synchronize()
     ref = _results(plan, len(grids))
     _reset(entries, fields)
-    plan.apply_persistent()
+    plan.apply()
     plan.check_persistent()
     for i in range(len(grids)):
         assert torch.equal(plan.result(i).interior(), ref[i]), i
@@ -229,24 +231,24 @@ def test_persistent_batch_repeated_launches_stay_exact():
     for depth, rows in [(8, 256), (3, 128), (5, 32)]:
         plan.set_tiles(depth, rows)
         _reset(entries, fields)
-        plan.apply()
+        plan.apply_passes()
         torch.cuda.synchronize()
         ref = _results(plan, len(grids))
         _reset(entries, fields)
-        plan.apply()
-        plan.apply()
+        plan.apply_passes()
+        plan.apply_passes()
         torch.cuda.synchronize()
         ref2 = _results(plan, len(grids))
         for rep in range(4):
             _reset(entries, fields)
-            plan.apply_persistent()
+            plan.apply()
             plan.check_persistent()
             bad = [i for i in range(len(grids)) if not torch.equal(plan.result(i).interior(), ref[i])]
             assert not bad, (depth, rows, rep, bad[:5])
         for rep in range(2):
             _reset(entries, fields)
-            plan.apply_persistent()
-            plan.apply_persistent()
+            plan.apply()
+            plan.apply()
             plan.check_persistent()
             bad = [i for i in range(len(grids)) if not torch.equal(plan.result(i).interior(), ref2[i])]
             assert not bad, (depth, rows, "two in a row", rep, bad[:5])
