@@ -161,7 +161,7 @@ def measure_batch(reps=3, per_grid=True, by_depth_sweep=True):
     # batch's dtype and size (what lope_batch_apply does by default): every
     # pass of every grid in one persistent kernel launch
     depth, rows = plan.tiles()
-    tb = timed(plan.apply, warm=10)   # the first launches after set-up run slower
+    tb = timed(plan.apply, warm=20)   # the first launches after set-up run slower
     plan.check_persistent()
     # the same sweeps as one launch per fused pass (a recorded graph), at the
     # same tiling and at the tiling measured fastest for it (6 per pass,
