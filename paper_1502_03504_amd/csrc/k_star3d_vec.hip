@@ -347,6 +347,7 @@ const Variant kStar3dVec[] = {
     VSTAR(float, LOPE_F32, 1, 128, 32, 512, 1, 32),
     VSTAR(float, LOPE_F32, 1, 256, 16, 512, 2, 32),
     VSTAR(float, LOPE_F32, 1, 256, 32, 1024, 1, 64),
+    VSTARH(float, LOPE_F32, 1, 256, 32, 1024, 1, 2, "1h2", 64, 1),
     VSTARH(float, LOPE_F32, 1, 128, 32, 512, 1, 2, "1h2", 64, 1),
     VSTAR(float, LOPE_F32, 2, 64, 32, 256, 1, 64),
     VSTAR(float, LOPE_F32, 3, 64, 32, 256, 1, 64),
