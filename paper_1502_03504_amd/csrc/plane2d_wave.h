@@ -12,11 +12,12 @@
 // three rows in registers with their left and right neighbours (nine values);
 // at march step j level 0 receives row j and level k computes row j - k from
 // level k-1's rows j-k-1 .. j-k+1, all in the same step (levels ascending).
-// The march is unrolled by six so every ring slot is a fixed register, and
-// rows are prefetched six steps ahead (the loads in flight per wave are what
-// keeps HBM busy: the wave has no other source of memory parallelism).  No LDS, no barriers.  Each point is
-// c0*v0 followed by fmas in lexicographic offset order (x fastest), the same
-// as every other kernel.
+// The march is unrolled by six (twelve with DEV) so every ring slot is a
+// fixed register, and rows are prefetched as many steps ahead (the loads in
+// flight per wave are what keeps HBM busy: the wave has no other source of
+// memory parallelism).  No LDS, no barriers.  Each point is c0*v0 followed
+// by fmas in lexicographic offset order (x fastest), the same as every other
+// kernel.
 //
 // Boundary rule: along a periodic axis the loaded column or row is the wrapped
 // one; a lane outside the interior along a Dirichlet x axis (DX) holds g at
@@ -144,8 +145,9 @@ __device__ __forceinline__ void plane2d_wave_strip(const DevGrid& src, const Dev
     const int jstart = y0 - G;
     const int jlast_load = yend - 1 + G;
     const int jend = yend - 1 + TD;
-    // rows are loaded PF march steps ahead (PF a multiple of the ring length)
-    constexpr int PF = 6;
+    // rows are loaded PF march steps ahead (PF a multiple of the ring length;
+    // device-scope loads, which miss in L2, twice as far)
+    constexpr int PF = DEV ? 12 : 6;
     T pf[PF];
 #pragma unroll
     for (int s = 0; s < PF; ++s) pf[s] = (jstart + s <= jlast_load) ? next_row() : g;
