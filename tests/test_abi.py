@@ -560,3 +560,21 @@ def test_batch_tune_set_validation_and_cache(tmp_path):
     path.write_text(json.dumps(cache))
     assert tune.register_cache(str(path)) == 1
     assert L.lope_batch_tune_set(F32, 1 << 21, 0, 0) == 0
+
+
+def test_committed_tuning_table_names_built_variants():
+    """Every kernel entry of the committed gfx950 table names a variant the
+    library builds (a removed build must leave no stale entry), and every
+    batch entry holds a depth and strip height the batch plan accepts."""
+    import json
+
+    import paper_1502_03504_amd as pkg
+    with open(os.path.join(ROOT, "paper_1502_03504_amd", "tuned_gfx950.json")) as f:
+        table = json.load(f)
+    built = {info.split()[0] for info in pkg.variants()}
+    assert table
+    for key, entry in table.items():
+        if "|batch|" in key:
+            assert 1 <= entry["tdepth"] <= 8 and 1 <= entry["rows"] <= 65536, key
+        else:
+            assert entry["variant"] in built, (key, entry["variant"])
